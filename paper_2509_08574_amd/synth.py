@@ -1,0 +1,185 @@
+"""Seeded synthetic inputs: workload configurations, phantoms, noise, random vectors.
+
+This module is shared by the tests, the benchmark and the oracle checks.  It
+holds none of the reconstruction method's arithmetic: it draws phantoms
+(voxelised ellipsoids and needle cylinders), random test vectors and
+measurement noise applied to line integrals computed elsewhere.  Everything is
+seeded through ``numpy.random.default_rng``.
+
+Phantom recipe (the paper's own data -- the TIGRE head phantom and the thorax
+scan with its 3D Slicer ground truth -- is not available, so these stand in):
+* ellipsoids with uniformly random orientation (random unit quaternion),
+  centres uniform in the inner 70 % of the volume, semi-axes uniform in the
+  configured range (voxels), densities U[0.1, 1.0], added together;
+* voxelisation by the voxel-centre test;
+* a needle is a finite cylinder whose voxels are *set* to its value (2.0);
+* noise: counts ~ Poisson(I0 exp(-mu p)) with mu = 0.02 / mm per density unit,
+  counts clamped to >= 1, b = -ln(counts / I0) / mu.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+MU_WATER_PER_MM = 0.02
+
+
+def _rotation(rng) -> np.ndarray:
+    q = rng.normal(size=4)
+    q /= np.linalg.norm(q)
+    w, x, y, z = q
+    return np.array([
+        [1 - 2 * (y * y + z * z), 2 * (x * y - z * w), 2 * (x * z + y * w)],
+        [2 * (x * y + z * w), 1 - 2 * (x * x + z * z), 2 * (y * z - x * w)],
+        [2 * (x * z - y * w), 2 * (y * z + x * w), 1 - 2 * (x * x + y * y)],
+    ])
+
+
+def _grid(shape):
+    nz, ny, nx = shape
+    return (np.arange(nz) + 0.5, np.arange(ny) + 0.5, np.arange(nx) + 0.5)
+
+
+def add_ellipsoid(vol: np.ndarray, centre, semi, R, value, mode="add"):
+    """Voxel-centre voxelisation of {p : |R^T (p - c) / a| <= 1} (voxel units, (x,y,z))."""
+    nz, ny, nx = vol.shape
+    rmax = float(max(semi))
+    lo = [max(0, int(math.floor(centre[a] - rmax)) - 1) for a in range(3)]
+    hi = [min(n, int(math.ceil(centre[a] + rmax)) + 1) for a, n in enumerate((nx, ny, nz))]
+    if any(h <= l for l, h in zip(lo, hi)):
+        return
+    zc = np.arange(lo[2], hi[2]) + 0.5 - centre[2]
+    yc = np.arange(lo[1], hi[1]) + 0.5 - centre[1]
+    xc = np.arange(lo[0], hi[0]) + 0.5 - centre[0]
+    Z, Y, X = np.meshgrid(zc, yc, xc, indexing="ij")
+    P = np.stack([X, Y, Z], axis=-1) @ R  # rows: R^T p
+    inside = ((P / np.asarray(semi)) ** 2).sum(axis=-1) <= 1.0
+    sub = vol[lo[2]:hi[2], lo[1]:hi[1], lo[0]:hi[0]]
+    if mode == "add":
+        sub[inside] += value
+    else:
+        sub[inside] = value
+
+
+def add_cylinder(vol: np.ndarray, centre, axis, radius, length, value):
+    """Set the voxels whose centres lie in a finite cylinder to ``value`` (voxel units)."""
+    nz, ny, nx = vol.shape
+    axis = np.asarray(axis, dtype=np.float64)
+    axis = axis / np.linalg.norm(axis)
+    ext = length / 2.0 + radius + 1
+    lo = [max(0, int(math.floor(centre[a] - ext))) for a in range(3)]
+    hi = [min(n, int(math.ceil(centre[a] + ext)) + 1) for a, n in enumerate((nx, ny, nz))]
+    if any(h <= l for l, h in zip(lo, hi)):
+        return
+    zc = np.arange(lo[2], hi[2]) + 0.5 - centre[2]
+    yc = np.arange(lo[1], hi[1]) + 0.5 - centre[1]
+    xc = np.arange(lo[0], hi[0]) + 0.5 - centre[0]
+    Z, Y, X = np.meshgrid(zc, yc, xc, indexing="ij")
+    P = np.stack([X, Y, Z], axis=-1)
+    t = P @ axis
+    r2 = (P ** 2).sum(axis=-1) - t * t
+    inside = (np.abs(t) <= length / 2.0) & (r2 <= radius * radius)
+    vol[lo[2]:hi[2], lo[1]:hi[1], lo[0]:hi[0]][inside] = value
+
+
+def ellipsoid_phantom(shape, n_ell, semi_range, seed, dens_range=(0.1, 1.0)):
+    """Sum of ``n_ell`` random ellipsoids; returns (volume, list of ellipsoid params)."""
+    rng = np.random.default_rng(seed)
+    nz, ny, nx = shape
+    vol = np.zeros(shape, dtype=np.float64)
+    ells = []
+    for _ in range(n_ell):
+        c = np.array([rng.uniform(0.15 * n, 0.85 * n) for n in (nx, ny, nz)])
+        a = rng.uniform(semi_range[0], semi_range[1], size=3)
+        R = _rotation(rng)
+        rho = rng.uniform(*dens_range)
+        ells.append((c, a, R, rho))
+        add_ellipsoid(vol, c, a, R, rho)
+    return vol, ells
+
+
+def random_unit(rng) -> np.ndarray:
+    v = rng.normal(size=3)
+    return v / np.linalg.norm(v)
+
+
+def noisy_line_integrals(p: np.ndarray, I0: float, seed: int, mu=MU_WATER_PER_MM):
+    """Poisson transmission noise on line integrals p (mm x density)."""
+    rng = np.random.default_rng(seed)
+    lam = I0 * np.exp(-mu * np.asarray(p, dtype=np.float64))
+    counts = np.maximum(rng.poisson(lam), 1).astype(np.float64)
+    return -np.log(counts / I0) / mu
+
+
+def random_volume(shape, seed, lo=0.0, hi=1.0):
+    return np.random.default_rng(seed).uniform(lo, hi, size=shape)
+
+
+def random_proj(shape, seed, lo=0.0, hi=1.0):
+    return np.random.default_rng(seed).uniform(lo, hi, size=shape)
+
+
+# --------------------------------------------------------------------------
+# Workload configurations.  Geometry keys match the C descriptor fields.
+
+def geometry(name: str) -> dict:
+    g = {
+        # 64^3 at 1 mm, 96x96 detector at 1.5 mm, 48 views.
+        "c1": dict(nx=64, ny=64, nz=64, vx=1.0, vy=1.0, vz=1.0, nu=96, nv=96, du=1.5, dv=1.5,
+                   dso=1000.0, dsd=1536.0, n_views=48),
+        # 256^3 at 1 mm, 512x512 at 0.8 mm, 90 views.
+        "c2": dict(nx=256, ny=256, nz=256, vx=1.0, vy=1.0, vz=1.0, nu=512, nv=512, du=0.8,
+                   dv=0.8, dso=1000.0, dsd=1536.0, n_views=90),
+        # 720-view scan of the same object (prior acquisition).
+        "c2_prior": dict(nx=256, ny=256, nz=256, vx=1.0, vy=1.0, vz=1.0, nu=512, nv=512,
+                         du=0.8, dv=0.8, dso=1000.0, dsd=1536.0, n_views=720),
+        # 512^3 at 0.5 mm, 1024x768 at 0.4 mm, 120 views.
+        "c3_512": dict(nx=512, ny=512, nz=512, vx=0.5, vy=0.5, vz=0.5, nu=1024, nv=768,
+                       du=0.4, dv=0.4, dso=1000.0, dsd=1536.0, n_views=120),
+        # 512x512x400 at 0.4 mm, 1024x1024 at 0.3 mm, 180 views.
+        "c5": dict(nx=512, ny=512, nz=400, vx=0.4, vy=0.4, vz=0.4, nu=1024, nv=1024, du=0.3,
+                   dv=0.3, dso=1000.0, dsd=1536.0, n_views=180),
+    }
+    return dict(g[name])
+
+
+def serving_geometry(n: int, n_views: int) -> dict:
+    """Serving-stream geometry: FOV 256 mm, voxel 256/n mm, detector 2n x 2n at 0.8*256/n mm."""
+    h = 256.0 / n
+    return dict(nx=n, ny=n, nz=n, vx=h, vy=h, vz=h, nu=2 * n, nv=2 * n, du=0.8 * h,
+                dv=0.8 * h, dso=1000.0, dsd=1536.0, n_views=n_views)
+
+
+# Regularisation parameters (alpha, lambda, tau) and the outer x inner split of
+# the iteration count per workload.
+SOLVE_PARAMS = {
+    "c1": dict(alpha=1.0, lam=2.0, tau=0.1, n_outer=3, n_inner=5, I0=1e5, seed=1),
+    "c2": dict(alpha=1.0, lam=2.0, tau=0.1, n_outer=5, n_inner=10, I0=5e4, seed=2),
+    "c5": dict(alpha=1.0, lam=2.0, tau=0.1, n_outer=4, n_inner=10, I0=5e4, seed=5),
+}
+
+
+def c1_case(seed: int = 1):
+    """The 64^3 / 48-view case: prior, current object (prior + sphere + needle)."""
+    shape = (64, 64, 64)
+    prior, _ = ellipsoid_phantom(shape, 10, (4.0, 24.0), seed)
+    rng = np.random.default_rng(seed + 1000)
+    cur = prior.copy()
+    c = np.array([rng.uniform(0.3 * 64, 0.7 * 64) for _ in range(3)])
+    add_ellipsoid(cur, c, (4.0, 4.0, 4.0), np.eye(3), 0.5)
+    nc = np.array([rng.uniform(0.35 * 64, 0.65 * 64) for _ in range(3)])
+    add_cylinder(cur, nc, random_unit(rng), 1.0, 40.0, 2.0)
+    return prior, cur
+
+
+def c2_case(seed: int = 2):
+    """The 256^3 / 90-view case: 30-ellipsoid object and its lesion-growth change."""
+    shape = (256, 256, 256)
+    base, ells = ellipsoid_phantom(shape, 30, (16.0, 96.0), seed)
+    k = int(np.argmin([np.prod(a) for (_, a, _, _) in ells]))
+    c, a, R, rho = ells[k]
+    cur = base.copy()
+    add_ellipsoid(cur, c, a, R, -rho)          # remove the original lesion
+    add_ellipsoid(cur, c, 1.3 * a, R, rho)     # and add it grown by 1.3
+    return base, cur
