@@ -1,0 +1,202 @@
+// Geometry handle: validation, float64 -> float32 ray tables, per-device upload.
+#include <cmath>
+#include <cstring>
+
+#include "internal.h"
+
+namespace cbct {
+
+static thread_local std::string g_last_error;
+
+void set_last_error(const std::string &msg) { g_last_error = msg; }
+void clear_last_error() { g_last_error.clear(); }
+
+// Coefficients (c0, r) of one axis of a ray written as
+//   index position(a') = c0 + a' / r,  a' = alpha - a_ref,
+// from the source coordinate S, direction component d (P - S) and the grid's
+// low edge lo and cell size h.  Plane p is crossed at a' = (p - c0) * r.
+static void axis_coeffs(double S, double d, double lo, double h, double a_ref, float &c0,
+                        float &r) {
+    const double dpos = d / h;                     // index units per unit alpha
+    const double pos_ref = (S - lo) / h + a_ref * dpos;  // index position at a' = 0
+    c0 = (float)pos_ref;
+    // A ray parallel to the planes never crosses them: a huge finite slope keeps
+    // (p - c0) * r finite and far outside any traversal interval.
+    r = std::fabs(dpos) > 1e-30 ? (float)(1.0 / dpos) : 1e30f;
+}
+
+static void build_tables(cbct_geom *g) {
+    const cbct_geom_desc &d = g->d;
+    const double a_ref = d.dso / d.dsd;
+    const double xlo = -d.nx * d.vx / 2.0, ylo = -d.ny * d.vy / 2.0, zlo = -d.nz * d.vz / 2.0;
+    g->xy.resize((size_t)d.n_views * d.nu);
+    g->trig.resize((size_t)d.n_views);
+    for (int v = 0; v < d.n_views; ++v) {
+        const double th = g->angles[(size_t)v];
+        const double c = std::cos(th), s = std::sin(th);
+        g->trig[(size_t)v] = make_float2((float)c, (float)s);
+        const double Sx = d.dso * c, Sy = d.dso * s;
+        for (int iu = 0; iu < d.nu; ++iu) {
+            const double u = (iu + 0.5) * d.du - d.nu * d.du / 2.0;
+            const double Px = (d.dso - d.dsd) * c - u * s;
+            const double Py = (d.dso - d.dsd) * s + u * c;
+            float4 e;
+            axis_coeffs(Sx, Px - Sx, xlo, d.vx, a_ref, e.x, e.y);
+            axis_coeffs(Sy, Py - Sy, ylo, d.vy, a_ref, e.z, e.w);
+            g->xy[(size_t)v * d.nu + iu] = e;
+        }
+    }
+    g->zr.resize((size_t)d.nv);
+    g->Lv2.resize((size_t)d.nv);
+    for (int iv = 0; iv < d.nv; ++iv) {
+        const double vmm = (iv + 0.5) * d.dv - d.nv * d.dv / 2.0;
+        float z0, rg;
+        axis_coeffs(0.0, vmm, zlo, d.vz, a_ref, z0, rg);
+        const double dz = vmm / d.vz;
+        const float s = rg > 0.0f ? 1.0f : -1.0f;
+        g->zr[(size_t)iv] = make_float4(z0, rg, (float)dz, s);
+        g->Lv2[(size_t)iv] = (float)(vmm * vmm);
+    }
+    g->Lu2.resize((size_t)d.nu);
+    for (int iu = 0; iu < d.nu; ++iu) {
+        const double u = (iu + 0.5) * d.du - d.nu * d.du / 2.0;
+        g->Lu2[(size_t)iu] = (float)(d.dsd * d.dsd + u * u);
+    }
+}
+
+static void validate(const cbct_geom_desc *d) {
+    CBCT_REQUIRE(d != nullptr, "null geometry descriptor");
+    CBCT_REQUIRE(d->nx > 0 && d->ny > 0 && d->nz > 0, "volume sizes must be > 0");
+    CBCT_REQUIRE(d->nu > 0 && d->nv > 0 && d->n_views > 0, "detector sizes and n_views must be > 0");
+    CBCT_REQUIRE(d->vx > 0 && d->vy > 0 && d->vz > 0, "voxel sizes must be > 0");
+    CBCT_REQUIRE(d->du > 0 && d->dv > 0, "detector pitch must be > 0");
+    CBCT_REQUIRE(std::isfinite(d->dso) && std::isfinite(d->dsd) && d->dso > 0 && d->dsd > d->dso,
+                 "need 0 < DSO < DSD");
+    CBCT_REQUIRE(d->nx <= 8192 && d->ny <= 8192 && d->nz <= 8192, "volume side > 8192");
+    CBCT_REQUIRE(d->nu <= 16384 && d->nv <= 16384 && d->n_views <= 65536,
+                 "detector or view count too large");
+    CBCT_REQUIRE((int64_t)d->n_views * d->nu * d->nv < (int64_t)1 << 40, "too many rays");
+    const double hx = d->nx * d->vx / 2, hy = d->ny * d->vy / 2, hz = d->nz * d->vz / 2;
+    const double rsph = std::sqrt(hx * hx + hy * hy + hz * hz);
+    const double rxy = std::sqrt(hx * hx + hy * hy);
+    CBCT_REQUIRE(d->dso > rsph, "source inside the volume's bounding sphere");
+    CBCT_REQUIRE(d->dsd - d->dso > rxy, "detector intersects the volume");
+    // At most one z plane per x-y cell: z moves by |v|/DSD per mm of x-y path
+    // at most, and a ray's path through one x-y cell is at most the cell diagonal.
+    const double vmax = d->nv * d->dv / 2.0;
+    const double diag = std::sqrt(d->vx * d->vx + d->vy * d->vy);
+    CBCT_REQUIRE(vmax / d->dsd * diag < 0.95 * d->vz,
+                 "cone angle too large for the column traversal (a ray would cross more than "
+                 "one z plane inside one x-y cell)");
+    if (d->angles)
+        for (int v = 0; v < d->n_views; ++v)
+            CBCT_REQUIRE(std::isfinite(d->angles[v]), "non-finite view angle");
+}
+
+GeoK geo_for_device(cbct_geom *g) {
+    int dev = 0;
+    CBCT_HIP(hipGetDevice(&dev));
+    DevTables t;
+    {
+        std::lock_guard<std::mutex> lk(g->mu);
+        auto it = g->dev.find(dev);
+        if (it == g->dev.end()) {
+            const cbct_geom_desc &d = g->d;
+            try {
+                CBCT_HIP(hipMalloc(&t.xy, sizeof(float4) * g->xy.size()));
+                CBCT_HIP(hipMalloc(&t.zr, sizeof(float4) * g->zr.size()));
+                CBCT_HIP(hipMalloc(&t.Lu2, sizeof(float) * g->Lu2.size()));
+                CBCT_HIP(hipMalloc(&t.Lv2, sizeof(float) * g->Lv2.size()));
+                CBCT_HIP(hipMalloc(&t.trig, sizeof(float2) * g->trig.size()));
+                CBCT_HIP(hipMemcpy(t.xy, g->xy.data(), sizeof(float4) * g->xy.size(),
+                                   hipMemcpyHostToDevice));
+                CBCT_HIP(hipMemcpy(t.zr, g->zr.data(), sizeof(float4) * g->zr.size(),
+                                   hipMemcpyHostToDevice));
+                CBCT_HIP(hipMemcpy(t.Lu2, g->Lu2.data(), sizeof(float) * d.nu,
+                                   hipMemcpyHostToDevice));
+                CBCT_HIP(hipMemcpy(t.Lv2, g->Lv2.data(), sizeof(float) * d.nv,
+                                   hipMemcpyHostToDevice));
+                CBCT_HIP(hipMemcpy(t.trig, g->trig.data(), sizeof(float2) * g->trig.size(),
+                                   hipMemcpyHostToDevice));
+            } catch (...) {
+                (void)hipFree(t.xy); (void)hipFree(t.zr); (void)hipFree(t.Lu2);
+                (void)hipFree(t.Lv2); (void)hipFree(t.trig);
+                throw;
+            }
+            g->dev[dev] = t;
+        } else {
+            t = it->second;
+        }
+    }
+    const cbct_geom_desc &d = g->d;
+    GeoK G;
+    G.nx = d.nx; G.ny = d.ny; G.nz = d.nz; G.nu = d.nu; G.nv = d.nv; G.nviews = d.n_views;
+    G.Z = d.nz + 2;
+    G.hx = (float)d.vx; G.hy = (float)d.vy;
+    G.dso = (float)d.dso; G.dsd = (float)d.dsd; G.du = (float)d.du; G.dv = (float)d.dv;
+    G.xy = t.xy; G.zr = t.zr; G.Lu2 = t.Lu2; G.Lv2 = t.Lv2; G.trig = t.trig;
+    return G;
+}
+
+}  // namespace cbct
+
+using namespace cbct;
+
+extern "C" {
+
+const char *cbct_last_error(void) { return g_last_error.c_str(); }
+
+int cbct_geom_create(const cbct_geom_desc *d, cbct_geom **out) {
+    try {
+        clear_last_error();
+        CBCT_REQUIRE(out != nullptr, "null output handle");
+        *out = nullptr;
+        validate(d);
+        cbct_geom *g = new cbct_geom();
+        g->d = *d;
+        g->angles.resize((size_t)d->n_views);
+        for (int v = 0; v < d->n_views; ++v)
+            g->angles[(size_t)v] = d->angles ? d->angles[v] : 2.0 * M_PI * v / d->n_views;
+        g->d.angles = g->angles.data();
+        build_tables(g);
+        *out = g;
+        return CBCT_OK;
+    } catch (const Error &e) {
+        set_last_error(e.what());
+        return e.code;
+    } catch (const std::bad_alloc &) {
+        set_last_error("host allocation failed");
+        return CBCT_ERR_OOM;
+    } catch (const std::exception &e) {
+        set_last_error(e.what());
+        return CBCT_ERR_INVALID;
+    }
+}
+
+void cbct_geom_destroy(cbct_geom *g) {
+    if (!g) return;
+    int cur = 0;
+    (void)hipGetDevice(&cur);
+    for (auto &kv : g->dev) {
+        (void)hipSetDevice(kv.first);
+        (void)hipFree(kv.second.xy);
+        (void)hipFree(kv.second.zr);
+        (void)hipFree(kv.second.Lu2);
+        (void)hipFree(kv.second.Lv2);
+        (void)hipFree(kv.second.trig);
+    }
+    (void)hipSetDevice(cur);
+    delete g;
+}
+
+int cbct_geom_sizes(const cbct_geom *g, int64_t *n_vox, int64_t *n_proj) {
+    if (!g) {
+        set_last_error("null geometry");
+        return CBCT_ERR_INVALID;
+    }
+    if (n_vox) *n_vox = g->n_vox();
+    if (n_proj) *n_proj = g->n_proj();
+    return CBCT_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,129 @@
+// Internal declarations of the CBCT HIP library (not part of the public ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <map>
+#include <mutex>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/cbct.h"
+
+namespace cbct {
+
+// Error carrying a C status code; converted at the ABI boundary.
+struct Error : std::runtime_error {
+    int code;
+    Error(int c, const std::string &m) : std::runtime_error(m), code(c) {}
+};
+
+void set_last_error(const std::string &msg);
+void clear_last_error();
+
+#define CBCT_HIP(call)                                                                  \
+    do {                                                                                \
+        hipError_t e_ = (call);                                                         \
+        if (e_ != hipSuccess)                                                           \
+            throw ::cbct::Error(e_ == hipErrorOutOfMemory ? CBCT_ERR_OOM : CBCT_ERR_DEVICE, \
+                                std::string(#call) + ": " + hipGetErrorString(e_));     \
+    } while (0)
+
+#define CBCT_REQUIRE(cond, msg)                                                         \
+    do {                                                                                \
+        if (!(cond)) throw ::cbct::Error(CBCT_ERR_INVALID, msg);                        \
+    } while (0)
+
+// Number of zero floats before and after every padded volume buffer.
+constexpr int kGuard = 64;
+
+// Kernel-side view of a geometry on one device (passed by value).
+//
+// Internal layouts used by every kernel:
+//  * "column" volumes: cell (i, j, k) at P[(j*nx + i)*Z + k + 1] with Z = nz + 2;
+//    local entries 0 and Z-1 of each column are zero pads (cells k = -1 and
+//    k = nz), and kGuard zero floats precede and follow the array;
+//  * "column" projections: sample (view, iu, iv) at Y[(view*nu + iu)*nv + iv].
+struct GeoK {
+    int nx, ny, nz, nu, nv, nviews;
+    int Z;               // nz + 2
+    float hx, hy;        // voxel size in x, y [mm] (detector footprint only)
+    float dso, dsd, du, dv;
+    const float4 *xy;    // [nviews*nu]: (xi0, rx, eta0, ry) -- see geom.cpp
+    const float4 *zr;    // [nv]: (z0, rg, dz, s)
+    const float *Lu2;    // [nu]: dsd^2 + u^2
+    const float *Lv2;    // [nv]: v^2
+    const float2 *trig;  // [nviews]: (cos th, sin th)
+};
+
+struct DevTables {
+    float4 *xy = nullptr;
+    float4 *zr = nullptr;
+    float *Lu2 = nullptr;
+    float *Lv2 = nullptr;
+    float2 *trig = nullptr;
+};
+
+}  // namespace cbct
+
+struct cbct_geom {
+    cbct_geom_desc d{};
+    std::vector<double> angles;
+    // Host copies of the float32 tables (built once in cbct_geom_create).
+    std::vector<float4> xy;
+    std::vector<float4> zr;
+    std::vector<float> Lu2, Lv2;
+    std::vector<float2> trig;
+    std::mutex mu;
+    std::map<int, cbct::DevTables> dev;
+
+    int64_t n_vox() const { return (int64_t)d.nx * d.ny * d.nz; }
+    int64_t n_proj() const { return (int64_t)d.n_views * d.nv * d.nu; }
+    int64_t n_col() const { return (int64_t)d.nx * d.ny; }
+    int Z() const { return d.nz + 2; }
+    // floats in one padded column volume buffer, guards included
+    int64_t pad_floats() const { return n_col() * Z() + 2 * cbct::kGuard; }
+};
+
+namespace cbct {
+
+// Kernel arguments for geometry g on the current device (uploads tables once).
+GeoK geo_for_device(cbct_geom *g);
+
+// ---- projector launchers (proj.hip) ----
+// Forward epilogue modes.
+enum FwdMode { FWD_PLAIN = 0, FWD_SOLVER = 1, FWD_COUNT = 2 };
+
+struct FwdArgs {
+    const float *vol;        // padded column volume base (cell (col, -1))
+    float *out;              // column projections
+    const float *uin;        // FWD_SOLVER: previous u-hat (may alias out)
+    const double *s1, *s2;   // FWD_SOLVER: device scalars
+    double *partial;         // FWD_SOLVER: one double per block
+    const int *brk;          // FWD_SOLVER: breakdown flag (2 = stopped)
+    unsigned long long *count;  // FWD_COUNT
+};
+void launch_forward(const GeoK &G, int mode, const FwdArgs &a, hipStream_t s);
+int64_t forward_blocks(const GeoK &G);
+
+// Back projection of column projections y-hat (already multiplied by the ray
+// length L) into a padded column volume (pads written as zero).
+void launch_back(const GeoK &G, const float *yhat, float *out, const int *brk, hipStream_t s);
+
+// Batched 2-D transpose: out[b*ob + c*oc + r + ooff] = in[b*ib + r*ir + c + ioff] (* L(c,r)
+// when Lu2/Lv2 are non-null: used for projections with u = c, v = r).
+void launch_transpose(const float *in, float *out, int B, int R, int C, int64_t ib, int64_t ir,
+                      int64_t ioff, int64_t ob, int64_t oc, int64_t ooff, const float *Lu2,
+                      const float *Lv2, hipStream_t s);
+void launch_fill(float *p, int64_t n, float v, hipStream_t s);
+
+// API-layout <-> column-layout helpers.
+void vol_to_cols(const GeoK &G, const float *x, float *cols, hipStream_t s);
+void cols_to_vol(const GeoK &G, const float *cols, float *x, hipStream_t s);
+void proj_to_cols(const GeoK &G, const float *y, float *ycol, bool scale_by_L, hipStream_t s);
+void cols_to_proj(const GeoK &G, const float *ycol, float *y, hipStream_t s);
+
+}  // namespace cbct

@@ -1,0 +1,524 @@
+// IRN-PICCS solver on the device: TV weights, the regulariser blocks of the
+// augmented operator, LSQR's reductions and scalar recurrence, vector updates.
+//
+// Method (paper Sec. 2.2.2): for k = 1..n_outer, with W1 = W~(D x_{k-1}) and
+// W2 = W~(D x_{k-1} - D x_p), run n_inner LSQR iterations from x_{k-1} on
+//   A~ = [A; alpha W1 D; lambda W2 D],   b~ = [b; 0; lambda W2 D x_p].
+// LSQR (Paige & Saunders 1982) keeps u (data space) and v (model space)
+// unnormalised in storage: U = beta * u, V = alpha * v.  Every kernel reads its
+// scale factors from a float64 scalar block that the single-block reduction
+// kernels update, so the host enqueues the whole solve without waiting.
+//
+// Data-space vector: u_b (projections, stored as u-hat = L * u_b in column
+// layout, L = ray length), u1 and u2 (three difference components each, in
+// padded column volumes).  Model-space vectors: padded column volumes.
+#include <algorithm>
+#include <cmath>
+
+#include "chord.h"
+#include "internal.h"
+
+namespace cbct {
+
+enum Sc {
+    SC_ALPHA = 0, SC_BETA, SC_RHOBAR, SC_PHIBAR,
+    SC_FWD_S1, SC_FWD_S2, SC_REG_S1, SC_REG_S2, SC_BACK_S1, SC_BACK_S2,
+    SC_XW_A, SC_XW_B, SC_XW_C,
+    SC_M1, SC_P1, SC_ZERO,
+    SC_INNER_DONE, SC_OUTER_DONE, SC_NBRK,
+    SC_COUNT = 32
+};
+// flag 0: breakdown state of the current inner solve: 0 running, 1 last
+// update pending, 2 stopped.
+constexpr double kTiny = 1e-30;
+
+// ---------------------------------------------------------------- helpers
+
+struct VoxIdx {
+    int i, j, k;
+    bool ok;
+    int64_t c;  // index relative to the padded base P
+};
+
+__device__ __forceinline__ VoxIdx vox_index(const GeoK &G) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int nkb = (G.nz + 63) >> 6, nxb = (G.nx + 3) >> 2;
+    const unsigned b = blockIdx.x;
+    const int kb = (int)(b % (unsigned)nkb);
+    const unsigned t = b / (unsigned)nkb;
+    const int ib = (int)(t % (unsigned)nxb);
+    VoxIdx v;
+    v.j = (int)(t / (unsigned)nxb);
+    v.i = ib * 4 + w;
+    v.k = kb * 64 + lane;
+    v.ok = v.i < G.nx && v.k < G.nz;
+    v.c = ((int64_t)v.j * G.nx + v.i) * G.Z + v.k + 1;
+    return v;
+}
+
+static int64_t vox_blocks(const GeoK &G) {
+    return (int64_t)((G.nz + 63) / 64) * ((G.nx + 3) / 4) * G.ny;
+}
+
+// Sum of `v` over the block (256 threads), written to part[blockIdx.x].
+__device__ __forceinline__ void block_partial(double v, double *part) {
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    __shared__ double red[4];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (lane == 0) red[w] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) part[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+// ---------------------------------------------------------------- weights
+
+// w1 = (sqrt(|D x|^2) + tau^2)^(-1/2), w2 = (sqrt(|D x - D xp|^2) + tau^2)^(-1/2)
+// (paper Sec. 2.2.1, definition of W~*; Sec. 2.2.2 for the PICCS pair).
+__global__ void __launch_bounds__(256)
+k_weights(GeoK G, const float *__restrict__ x, const float *__restrict__ xp, float tau2,
+          float *__restrict__ w1, float *__restrict__ w2) {
+    const VoxIdx v = vox_index(G);
+    if (!v.ok) return;
+    const int64_t c = v.c, sy = (int64_t)G.nx * G.Z;
+    const float x0 = x[c], p0 = xp[c];
+    float gx = 0.f, gy = 0.f, gz = 0.f, hx = 0.f, hy = 0.f, hz = 0.f;
+    if (v.i < G.nx - 1) { gx = x0 - x[c + G.Z]; hx = gx - (p0 - xp[c + G.Z]); }
+    if (v.j < G.ny - 1) { gy = x0 - x[c + sy]; hy = gy - (p0 - xp[c + sy]); }
+    if (v.k < G.nz - 1) { gz = x0 - x[c + 1]; hz = gz - (p0 - xp[c + 1]); }
+    w1[c] = 1.0f / sqrtf(sqrtf(gx * gx + gy * gy + gz * gz) + tau2);
+    w2[c] = 1.0f / sqrtf(sqrtf(hx * hx + hy * hy + hz * hz) + tau2);
+}
+
+// ---------------------------------------------------------------- regulariser, forward
+
+// (u1, u2) <- s1 * (alpha W1 D v, lambda W2 D(v - vp)) + s2 * (u1, u2)
+// (the second and third blocks of A~ v, or of b~ - A~ x when vp is given);
+// partial sums of |u1|^2 + |u2|^2 per block.
+template <bool HAS_VP>
+__global__ void __launch_bounds__(256)
+k_regF(GeoK G, const float *__restrict__ V, const float *__restrict__ Vp,
+       const float *__restrict__ W1, const float *__restrict__ W2, float *__restrict__ u1,
+       float *__restrict__ u2, int64_t cstride, float alpha, float lam, const double *s1p,
+       const double *s2p, double *part, const int *brk) {
+    if (*brk == 2) return;
+    const VoxIdx v = vox_index(G);
+    const float s1 = (float)*s1p, s2 = (float)*s2p;
+    double sum = 0.0;
+    if (v.ok) {
+        const int64_t c = v.c, sy = (int64_t)G.nx * G.Z;
+        const float x0 = V[c];
+        float d[3] = {0.f, 0.f, 0.f}, e[3] = {0.f, 0.f, 0.f};
+        const float p0 = HAS_VP ? Vp[c] : 0.f;
+        if (v.i < G.nx - 1) {
+            d[0] = x0 - V[c + G.Z];
+            e[0] = HAS_VP ? d[0] - (p0 - Vp[c + G.Z]) : d[0];
+        }
+        if (v.j < G.ny - 1) {
+            d[1] = x0 - V[c + sy];
+            e[1] = HAS_VP ? d[1] - (p0 - Vp[c + sy]) : d[1];
+        }
+        if (v.k < G.nz - 1) {
+            d[2] = x0 - V[c + 1];
+            e[2] = HAS_VP ? d[2] - (p0 - Vp[c + 1]) : d[2];
+        }
+        const float a1 = alpha * W1[c], a2 = lam * W2[c];
+        float acc = 0.f;
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            float n1 = s1 * (a1 * d[q]);
+            float n2 = s1 * (a2 * e[q]);
+            if (s2 != 0.0f) {
+                n1 = fmaf(s2, u1[c + q * cstride], n1);
+                n2 = fmaf(s2, u2[c + q * cstride], n2);
+            }
+            u1[c + q * cstride] = n1;
+            u2[c + q * cstride] = n2;
+            acc = fmaf(n1, n1, acc);
+            acc = fmaf(n2, n2, acc);
+        }
+        sum = (double)acc;
+    }
+    block_partial(sum, part);
+}
+
+// ---------------------------------------------------------------- regulariser, adjoint
+
+// v <- s1 * (t + alpha D^T(W1 u1) + lambda D^T(W2 u2)) + s2 * v, with t = A^T u-hat
+// from the back projector; partial sums of |v|^2 per block.
+// D^T per axis: (D_1^T y)_i = y_i [i < n-1] - y_{i-1} [i >= 1].
+__global__ void __launch_bounds__(256)
+k_regA(GeoK G, const float *__restrict__ t, const float *__restrict__ W1,
+       const float *__restrict__ W2, const float *__restrict__ u1, const float *__restrict__ u2,
+       int64_t cstride, float alpha, float lam, float *__restrict__ V, const double *s1p,
+       const double *s2p, double *part, const int *brk) {
+    if (*brk == 2) return;
+    const VoxIdx v = vox_index(G);
+    const float s1 = (float)*s1p, s2 = (float)*s2p;
+    double sum = 0.0;
+    if (v.ok) {
+        const int64_t c = v.c;
+        const int64_t st[3] = {G.Z, (int64_t)G.nx * G.Z, 1};
+        const bool hi[3] = {v.i < G.nx - 1, v.j < G.ny - 1, v.k < G.nz - 1};
+        const bool lo[3] = {v.i > 0, v.j > 0, v.k > 0};
+        const float w1c = W1[c], w2c = W2[c];
+        float r1 = 0.f, r2 = 0.f;
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            const float *a = u1 + q * cstride;
+            const float *b = u2 + q * cstride;
+            if (hi[q]) {
+                r1 += w1c * a[c];
+                r2 += w2c * b[c];
+            }
+            if (lo[q]) {
+                r1 -= W1[c - st[q]] * a[c - st[q]];
+                r2 -= W2[c - st[q]] * b[c - st[q]];
+            }
+        }
+        float vn = s1 * (t[c] + alpha * r1 + lam * r2);
+        if (s2 != 0.0f) vn = fmaf(s2, V[c], vn);
+        V[c] = vn;
+        sum = (double)vn * (double)vn;
+    }
+    block_partial(sum, part);
+}
+
+// ---------------------------------------------------------------- vector updates
+
+// x += a w;  w <- b V + c w   (LSQR's solution and direction updates).  Works
+// on the whole padded array: pads are zero in every operand and stay zero.
+__global__ void __launch_bounds__(256)
+k_xw(float *__restrict__ x, float *__restrict__ w, const float *__restrict__ V, int64_t n,
+     const double *sc, const int *brk) {
+    if (*brk == 2) return;
+    const float a = (float)sc[SC_XW_A], b = (float)sc[SC_XW_B], c = (float)sc[SC_XW_C];
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += stride) {
+        const float wo = (a != 0.0f || c != 0.0f) ? w[t] : 0.0f;
+        if (a != 0.0f) x[t] = fmaf(a, wo, x[t]);
+        w[t] = fmaf(c, wo, b * V[t]);
+    }
+}
+
+// ---------------------------------------------------------------- reductions + recurrence
+
+enum RedMode { RED_INIT_BETA = 0, RED_INIT_ALPHA, RED_BETA, RED_ALPHA };
+
+// One block of 1024 threads: sum two partial arrays in a fixed order (so the
+// result is bit-reproducible), then advance LSQR's scalar recurrence.
+template <int MODE>
+__global__ void __launch_bounds__(1024)
+k_red(const double *__restrict__ p0, int64_t n0, const double *__restrict__ p1, int64_t n1,
+      double *sc, int *fl, double *hist, int it) {
+    const int brk = fl[0];
+    if (brk == 2) return;
+    if (MODE == RED_BETA && brk == 1) {
+        if (threadIdx.x == 0) fl[0] = 2;
+        return;
+    }
+    __shared__ double red[1024];
+    double s = 0.0;
+    for (int64_t t = threadIdx.x; t < n0; t += 1024) s += p0[t];
+    for (int64_t t = threadIdx.x; t < n1; t += 1024) s += p1[t];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int h = 512; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x != 0) return;
+    const double nrm = sqrt(red[0]);
+    if (MODE == RED_INIT_BETA) {            // beta_1 u_1 = b~ - A~ x_0
+        sc[SC_BETA] = nrm;
+        if (!(nrm > kTiny)) { fl[0] = 2; return; }
+        sc[SC_BACK_S1] = 1.0 / nrm;
+        sc[SC_BACK_S2] = 0.0;
+    } else if (MODE == RED_INIT_ALPHA) {    // alpha_1 v_1 = A~^T u_1; w_1 = v_1
+        sc[SC_ALPHA] = nrm;
+        if (!(nrm > kTiny)) { fl[0] = 2; return; }
+        const double beta = sc[SC_BETA];
+        sc[SC_PHIBAR] = beta;
+        sc[SC_RHOBAR] = nrm;
+        sc[SC_XW_A] = 0.0;
+        sc[SC_XW_B] = 1.0 / nrm;
+        sc[SC_XW_C] = 0.0;
+        sc[SC_FWD_S1] = sc[SC_REG_S1] = 1.0 / nrm;
+        sc[SC_FWD_S2] = sc[SC_REG_S2] = -nrm / beta;
+    } else if (MODE == RED_BETA) {          // beta u = A~ v - alpha u
+        const double alpha = sc[SC_ALPHA];
+        sc[SC_BETA] = nrm;
+        sc[SC_BACK_S1] = nrm > kTiny ? 1.0 / nrm : 1.0;
+        sc[SC_BACK_S2] = -nrm / alpha;
+    } else {                                 // alpha v = A~^T u - beta v; Givens; updates
+        const double beta = sc[SC_BETA], alpha = nrm;
+        const double rhobar = sc[SC_RHOBAR], phibar = sc[SC_PHIBAR];
+        const double rho = sqrt(rhobar * rhobar + beta * beta);
+        if (!(rho > 0.0)) { fl[0] = 2; return; }
+        const double c = rhobar / rho, s = beta / rho;
+        const double theta = s * alpha;
+        sc[SC_RHOBAR] = -c * alpha;
+        sc[SC_PHIBAR] = s * phibar;
+        const double phi = c * phibar;
+        sc[SC_XW_A] = phi / rho;
+        sc[SC_XW_B] = alpha > kTiny ? 1.0 / alpha : 0.0;
+        sc[SC_XW_C] = -theta / rho;
+        sc[SC_ALPHA] = alpha;
+        if (hist) hist[it] = s * phibar;
+        sc[SC_INNER_DONE] += 1.0;
+        if (!(beta > kTiny) || !(alpha > kTiny)) {
+            fl[0] = 1;  // apply this last update, then stop
+            sc[SC_FWD_S1] = sc[SC_FWD_S2] = sc[SC_REG_S1] = sc[SC_REG_S2] = 0.0;
+        } else {
+            sc[SC_FWD_S1] = sc[SC_REG_S1] = 1.0 / alpha;
+            sc[SC_FWD_S2] = sc[SC_REG_S2] = -alpha / beta;
+        }
+    }
+}
+
+__global__ void k_solve_begin(double *sc, int *fl, double *hist, int nh) {
+    for (int q = 0; q < SC_COUNT; ++q) sc[q] = 0.0;
+    for (int q = 0; q < nh; ++q) hist[q] = __longlong_as_double(0x7ff8000000000000LL);  // NaN
+    sc[SC_M1] = -1.0;
+    sc[SC_P1] = 1.0;
+    fl[0] = 0;
+}
+
+__global__ void k_outer_begin(double *sc, int *fl) {
+    if (fl[0] != 0) sc[SC_NBRK] += 1.0;
+    fl[0] = 0;
+    sc[SC_OUTER_DONE] += 1.0;
+}
+
+__global__ void k_solve_end(double *sc, int *fl) {
+    if (fl[0] != 0) sc[SC_NBRK] += 1.0;
+    fl[0] = 0;
+}
+
+// ---------------------------------------------------------------- workspace
+
+struct Workspace {
+    float *x, *xp, *w, *V, *t, *W1, *W2, *u1, *u2;  // padded column bases (P pointers)
+    int64_t cstride;                                // floats between components
+    float *bhat, *uhat;
+    double *pf, *pr, *pa;  // partials: forward, regF, regA
+    int64_t nf, nr;
+    double *sc, *hist;
+    int *fl;
+    size_t bytes;
+};
+
+static size_t al(size_t b) { return (b + 255) & ~(size_t)255; }
+
+static Workspace carve(const cbct_geom *g, const GeoK &G, const piccs_params *p, char *base) {
+    Workspace W{};
+    const size_t vb = al(sizeof(float) * (size_t)g->pad_floats());
+    const size_t pb = al(sizeof(float) * (size_t)g->n_proj());
+    W.nf = forward_blocks(G);
+    W.nr = vox_blocks(G);
+    size_t off = 0;
+    auto take = [&](size_t b) {
+        char *q = base ? base + off : nullptr;
+        off += al(b);
+        return q;
+    };
+    float *vols[13];
+    for (int q = 0; q < 13; ++q) vols[q] = (float *)take(vb);
+    auto P = [&](int q) { return vols[q] ? vols[q] + kGuard : nullptr; };
+    W.x = P(0); W.xp = P(1); W.w = P(2); W.V = P(3); W.t = P(4); W.W1 = P(5); W.W2 = P(6);
+    W.u1 = P(7); W.u2 = P(10);
+    W.cstride = (int64_t)(vb / sizeof(float));
+    W.bhat = (float *)take(pb);
+    W.uhat = (float *)take(pb);
+    W.pf = (double *)take(sizeof(double) * (size_t)W.nf);
+    W.pr = (double *)take(sizeof(double) * (size_t)W.nr);
+    W.pa = (double *)take(sizeof(double) * (size_t)W.nr);
+    W.sc = (double *)take(sizeof(double) * SC_COUNT);
+    W.fl = (int *)take(sizeof(int) * 16);
+    W.hist = (double *)take(sizeof(double) * (size_t)std::max(1, p->n_outer * p->n_inner));
+    W.bytes = off;
+    return W;
+}
+
+static void check_params(const piccs_params *p) {
+    CBCT_REQUIRE(p != nullptr, "null params");
+    CBCT_REQUIRE(std::isfinite(p->alpha) && p->alpha >= 0 && std::isfinite(p->lambda) &&
+                     p->lambda >= 0 && std::isfinite(p->tau) && p->tau >= 0,
+                 "alpha, lambda, tau must be finite and >= 0");
+    CBCT_REQUIRE(p->n_outer >= 1 && p->n_inner >= 1 && p->n_outer <= 100000 &&
+                     p->n_inner <= 100000, "n_outer and n_inner must be >= 1");
+    CBCT_REQUIRE(p->precision == CBCT_PREC_FP32,
+                 "only CBCT_PREC_FP32 is available in this build");
+    CBCT_REQUIRE(p->reorth == 0, "reorthogonalisation is not available in this build");
+}
+
+}  // namespace cbct
+
+using namespace cbct;
+
+namespace {
+
+int translate(const std::exception &ex) {
+    if (auto e = dynamic_cast<const Error *>(&ex)) {
+        set_last_error(e->what());
+        return e->code;
+    }
+    set_last_error(ex.what());
+    return CBCT_ERR_INVALID;
+}
+
+}  // namespace
+
+extern "C" {
+
+int piccs_weights(const cbct_geom *gc, const float *x, const float *xp, double tau, float *w1,
+                  float *w2, void *hip_stream) {
+    try {
+        clear_last_error();
+        CBCT_REQUIRE(gc && x && xp && w1 && w2, "null argument");
+        CBCT_REQUIRE(std::isfinite(tau) && tau >= 0, "tau must be finite and >= 0");
+        cbct_geom *g = const_cast<cbct_geom *>(gc);
+        hipStream_t s = (hipStream_t)hip_stream;
+        GeoK G = geo_for_device(g);
+        const int64_t pf = g->pad_floats();
+        float *tmp = nullptr;
+        CBCT_HIP(hipMallocAsync((void **)&tmp, sizeof(float) * 4 * pf, s));
+        try {
+            launch_fill(tmp, 4 * pf, 0.0f, s);
+            float *X = tmp + kGuard, *XP = tmp + pf + kGuard, *A = tmp + 2 * pf + kGuard,
+                  *B = tmp + 3 * pf + kGuard;
+            vol_to_cols(G, x, X, s);
+            vol_to_cols(G, xp, XP, s);
+            hipLaunchKernelGGL(k_weights, dim3((unsigned)vox_blocks(G)), dim3(256), 0, s, G, X,
+                               XP, (float)(tau * tau), A, B);
+            CBCT_HIP(hipGetLastError());
+            cols_to_vol(G, A, w1, s);
+            cols_to_vol(G, B, w2, s);
+        } catch (...) {
+            (void)hipFreeAsync(tmp, s);
+            throw;
+        }
+        CBCT_HIP(hipFreeAsync(tmp, s));
+        return CBCT_OK;
+    } catch (const std::exception &e) {
+        return translate(e);
+    }
+}
+
+int piccs_workspace_bytes(const cbct_geom *gc, const piccs_params *p, size_t *bytes) {
+    try {
+        clear_last_error();
+        CBCT_REQUIRE(gc && bytes, "null argument");
+        check_params(p);
+        cbct_geom *g = const_cast<cbct_geom *>(gc);
+        GeoK G{};
+        G.nx = g->d.nx; G.ny = g->d.ny; G.nz = g->d.nz; G.nu = g->d.nu; G.nv = g->d.nv;
+        G.nviews = g->d.n_views; G.Z = g->Z();
+        *bytes = carve(g, G, p, nullptr).bytes;
+        return CBCT_OK;
+    } catch (const std::exception &e) {
+        return translate(e);
+    }
+}
+
+int piccs_krylov_solve(const cbct_geom *gc, const float *b, const float *xp, float *x,
+                       const piccs_params *p, void *workspace, size_t ws_bytes,
+                       piccs_report *rep, void *hip_stream) {
+    try {
+        clear_last_error();
+        CBCT_REQUIRE(gc && b && xp && x && workspace, "null argument");
+        check_params(p);
+        CBCT_REQUIRE(((uintptr_t)workspace & 255) == 0, "workspace must be 256-byte aligned");
+        cbct_geom *g = const_cast<cbct_geom *>(gc);
+        hipStream_t s = (hipStream_t)hip_stream;
+        GeoK G = geo_for_device(g);
+        Workspace W = carve(g, G, p, (char *)workspace);
+        CBCT_REQUIRE(ws_bytes >= W.bytes, "workspace too small (see piccs_workspace_bytes)");
+
+        const int64_t pf = g->pad_floats();
+        const int64_t ncz = g->n_col() * G.Z;
+        const unsigned nvb = (unsigned)vox_blocks(G);
+        const float alpha = (float)p->alpha, lam = (float)p->lambda;
+        const float tau2 = (float)(p->tau * p->tau);
+
+        // padded column copies of the inputs (pads and guards zero)
+        launch_fill(W.x - kGuard, W.cstride * 13, 0.0f, s);
+        vol_to_cols(G, x, W.x, s);
+        vol_to_cols(G, xp, W.xp, s);
+        proj_to_cols(G, b, W.bhat, true, s);  // b-hat = L * b
+        hipLaunchKernelGGL(k_solve_begin, dim3(1), dim3(1), 0, s, W.sc, W.fl, W.hist,
+                           p->n_outer * p->n_inner);
+
+        FwdArgs fa{};
+        fa.out = W.uhat;
+        fa.uin = nullptr;
+        fa.partial = W.pf;
+        fa.brk = W.fl;
+        int it_global = 0;
+        for (int ko = 0; ko < p->n_outer; ++ko) {
+            hipLaunchKernelGGL(k_outer_begin, dim3(1), dim3(1), 0, s, W.sc, W.fl);
+            hipLaunchKernelGGL(k_weights, dim3(nvb), dim3(256), 0, s, G, W.x, W.xp, tau2, W.W1,
+                               W.W2);
+            // beta_1 u_1 = b~ - A~ x_{k-1}
+            fa.vol = W.x; fa.uin = W.bhat; fa.s1 = W.sc + SC_M1; fa.s2 = W.sc + SC_P1;
+            launch_forward(G, FWD_SOLVER, fa, s);
+            hipLaunchKernelGGL(k_regF<true>, dim3(nvb), dim3(256), 0, s, G, W.x, W.xp, W.W1,
+                               W.W2, W.u1, W.u2, W.cstride, alpha, lam, W.sc + SC_M1,
+                               W.sc + SC_ZERO, W.pr, W.fl);
+            hipLaunchKernelGGL(k_red<RED_INIT_BETA>, dim3(1), dim3(1024), 0, s, W.pf, W.nf,
+                               W.pr, W.nr, W.sc, W.fl, W.hist, 0);
+            // alpha_1 v_1 = A~^T u_1
+            launch_back(G, W.uhat, W.t, W.fl, s);
+            hipLaunchKernelGGL(k_regA, dim3(nvb), dim3(256), 0, s, G, W.t, W.W1, W.W2, W.u1,
+                               W.u2, W.cstride, alpha, lam, W.V, W.sc + SC_BACK_S1,
+                               W.sc + SC_BACK_S2, W.pa, W.fl);
+            hipLaunchKernelGGL(k_red<RED_INIT_ALPHA>, dim3(1), dim3(1024), 0, s, W.pa, W.nr,
+                               (const double *)nullptr, (int64_t)0, W.sc, W.fl, W.hist, 0);
+            hipLaunchKernelGGL(k_xw, dim3(4096), dim3(256), 0, s, W.x, W.w, W.V, ncz,
+                               W.sc, W.fl);
+            for (int ki = 0; ki < p->n_inner; ++ki, ++it_global) {
+                fa.vol = W.V; fa.uin = W.uhat; fa.s1 = W.sc + SC_FWD_S1; fa.s2 = W.sc + SC_FWD_S2;
+                launch_forward(G, FWD_SOLVER, fa, s);
+                hipLaunchKernelGGL(k_regF<false>, dim3(nvb), dim3(256), 0, s, G, W.V,
+                                   (const float *)nullptr, W.W1, W.W2, W.u1, W.u2, W.cstride,
+                                   alpha, lam, W.sc + SC_REG_S1, W.sc + SC_REG_S2, W.pr, W.fl);
+                hipLaunchKernelGGL(k_red<RED_BETA>, dim3(1), dim3(1024), 0, s, W.pf, W.nf,
+                                   W.pr, W.nr, W.sc, W.fl, W.hist, it_global);
+                launch_back(G, W.uhat, W.t, W.fl, s);
+                hipLaunchKernelGGL(k_regA, dim3(nvb), dim3(256), 0, s, G, W.t, W.W1, W.W2, W.u1,
+                                   W.u2, W.cstride, alpha, lam, W.V, W.sc + SC_BACK_S1,
+                                   W.sc + SC_BACK_S2, W.pa, W.fl);
+                hipLaunchKernelGGL(k_red<RED_ALPHA>, dim3(1), dim3(1024), 0, s, W.pa, W.nr,
+                                   (const double *)nullptr, (int64_t)0, W.sc, W.fl, W.hist,
+                                   it_global);
+                hipLaunchKernelGGL(k_xw, dim3(4096), dim3(256), 0, s, W.x, W.w, W.V, ncz,
+                                   W.sc, W.fl);
+            }
+        }
+        hipLaunchKernelGGL(k_solve_end, dim3(1), dim3(1), 0, s, W.sc, W.fl);
+        CBCT_HIP(hipGetLastError());
+        cols_to_vol(G, W.x, x, s);
+        (void)pf;
+
+        if (rep) {
+            std::vector<double> sc(SC_COUNT);
+            CBCT_HIP(hipMemcpyAsync(sc.data(), W.sc, sizeof(double) * SC_COUNT,
+                                    hipMemcpyDeviceToHost, s));
+            const int nh = p->n_outer * p->n_inner;
+            std::vector<double> hist((size_t)nh);
+            if (rep->resid_hist)
+                CBCT_HIP(hipMemcpyAsync(hist.data(), W.hist, sizeof(double) * nh,
+                                        hipMemcpyDeviceToHost, s));
+            CBCT_HIP(hipStreamSynchronize(s));
+            rep->inner_done = (int32_t)sc[SC_INNER_DONE];
+            rep->outer_done = (int32_t)sc[SC_OUTER_DONE];
+            rep->breakdown = (int32_t)sc[SC_NBRK];
+            if (rep->resid_hist)
+                for (int q = 0; q < nh; ++q) rep->resid_hist[q] = hist[(size_t)q];
+        }
+        return CBCT_OK;
+    } catch (const std::exception &e) {
+        return translate(e);
+    }
+}
+
+}  // extern "C"

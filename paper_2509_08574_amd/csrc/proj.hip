@@ -1,0 +1,560 @@
+// Cone-beam projector pair for gfx950: forward A and its exact transpose A^T.
+//
+// A is the sensing matrix of the linear CT model (paper Sec. 2.1, eq. "tomo"),
+// read as exact ray/voxel chord lengths; Krylov solvers touch it only through
+// products with A and A^T (Sec. 2.2.2).  Chord arithmetic: chord.h.
+//
+// Forward (k_fwd): one wave per (view, detector column u, 64 detector rows);
+// lane = row.  All rays of one detector column share their x-y path, so the
+// wave walks the voxel columns (i, j) it crosses in lock-step (uniform control
+// flow) while every lane tracks its own z cell.  Volumes are stored column-
+// major (z fastest), so at each step the 64 lanes read a short contiguous run
+// of one column: coalesced gathers for every view angle.
+//
+// Back (k_back): one wave per voxel column (i, j), four columns per block.
+// For every view, the wave visits the detector columns u whose rays cross
+// (i, j), recomputes the same x-y interval [aa, ab] and the same z state as
+// the forward kernel, and adds c0 * y to cell k and c1 * y to cell k + s of a
+// per-wave LDS copy of the column.  Each column is written to HBM once, with
+// no global atomics.
+#include <hip/hip_fp16.h>
+
+#include <algorithm>
+#include <cmath>
+
+#include "chord.h"
+#include "internal.h"
+
+namespace cbct {
+
+// ---------------------------------------------------------------- forward
+
+template <int MODE>
+__global__ void __launch_bounds__(256)
+k_fwd(GeoK G, FwdArgs a) {
+    if constexpr (MODE == FWD_SOLVER) {
+        if (*a.brk == 2) return;
+    }
+    const int lane = threadIdx.x & 63;
+    const int w = threadIdx.x >> 6;
+    const int nub = (G.nu + 3) >> 2, nrb = (G.nv + 63) >> 6;
+    const unsigned b = xcd_remap(blockIdx.x, gridDim.x);
+    const int ub = (int)(b % (unsigned)nub);
+    const unsigned t = b / (unsigned)nub;
+    const int rb = (int)(t % (unsigned)nrb);
+    const int view = (int)(t / (unsigned)nrb);
+    const int iu = ub * 4 + w, iv = rb * 64 + lane;
+    const int iuc = iu < G.nu ? iu : G.nu - 1;
+    const int ivc = iv < G.nv ? iv : G.nv - 1;
+
+    const float4 cxy = G.xy[(size_t)view * G.nu + iuc];
+    const float4 cz = G.zr[ivc];
+    const float ax0 = plane_alpha(0.0f, cxy.x, cxy.y), axN = plane_alpha((float)G.nx, cxy.x, cxy.y);
+    const float ay0 = plane_alpha(0.0f, cxy.z, cxy.w), ayN = plane_alpha((float)G.ny, cxy.z, cxy.w);
+    const float a_in = fmaxf(fminf(ax0, axN), fminf(ay0, ayN));
+    const float a_out = fminf(fmaxf(ax0, axN), fmaxf(ay0, ayN));
+
+    float acc = 0.0f;
+    unsigned cnt = 0;
+    if (a_out > a_in) {
+        const int sx = cxy.y > 0.0f ? 1 : -1, sy = cxy.w > 0.0f ? 1 : -1;
+        int i = xy_cell(a_in, cxy.x, cxy.y, G.nx);
+        int j = xy_cell(a_in, cxy.z, cxy.w, G.ny);
+        float axn = plane_alpha((float)(i + (sx > 0)), cxy.x, cxy.y);
+        float ayn = plane_alpha((float)(j + (sy > 0)), cxy.z, cxy.w);
+        float aa = a_in;
+        int k;
+        float pe, an;
+        zlane_init(aa, cz, G.nz, k, pe, an);
+        const float s = cz.w;
+        const int si = s > 0.0f ? 1 : -1;
+        int kk = k + 1;  // local index in the padded column
+        const int kmax = G.nz + 1;
+        const int nit = G.nx + G.ny + 2;
+        for (int it = 0; it < nit; ++it) {
+            const float ab = fminf(axn, ayn);
+            const int col = __builtin_amdgcn_readfirstlane(j * G.nx + i);
+            const float *colp = a.vol + (size_t)col * G.Z;
+            const float m = fminf(ab, an);
+            const float c0 = m - aa;
+            const float c1 = ab - m;
+            const float v0 = colp[kk];
+            const float v1 = colp[kk + si];
+            if constexpr (MODE == FWD_COUNT) {
+                cnt += (c0 > 0.0f && kk >= 1 && kk <= G.nz) ? 1u : 0u;
+                cnt += (c1 > 0.0f && kk + si >= 1 && kk + si <= G.nz) ? 1u : 0u;
+            } else {
+                acc = fmaf(c0, v0, acc);
+                acc = fmaf(c1, v1, acc);
+            }
+            if (an < ab) {
+                pe += s;
+                an = plane_alpha(pe, cz.x, cz.y);
+                kk = min(max(kk + si, 0), kmax);
+            }
+            const bool adx = axn == ab, ady = ayn == ab;
+            if (adx) {
+                i += sx;
+                axn = plane_alpha((float)(i + (sx > 0)), cxy.x, cxy.y);
+            }
+            if (ady) {
+                j += sy;
+                ayn = plane_alpha((float)(j + (sy > 0)), cxy.z, cxy.w);
+            }
+            if ((unsigned)i >= (unsigned)G.nx || (unsigned)j >= (unsigned)G.ny) break;
+            aa = ab;
+        }
+    }
+
+    const bool ok = iu < G.nu && iv < G.nv;
+    if constexpr (MODE == FWD_COUNT) {
+        if (ok && cnt) atomicAdd(a.count, (unsigned long long)cnt);
+        return;
+    }
+    const size_t o = ((size_t)view * G.nu + iuc) * G.nv + ivc;
+    const float L2 = G.Lu2[iuc] + G.Lv2[ivc];
+    if constexpr (MODE == FWD_PLAIN) {
+        if (ok) a.out[o] = sqrtf(L2) * acc;
+    } else {
+        // u-hat = L * u with u = s1 * (A v) + s2 * u_old  =>  u-hat = s1 L^2 acc + s2 u-hat_old
+        const float s1 = (float)*a.s1, s2 = (float)*a.s2;
+        float un = s1 * (L2 * acc);
+        if (s2 != 0.0f) un = fmaf(s2, a.uin[o], un);
+        double sq = 0.0;
+        if (ok) {
+            a.out[o] = un;
+            sq = (double)un * (double)un / (double)L2;  // |u|^2 = u-hat^2 / L^2
+        }
+        // block reduction (fixed order -> deterministic)
+        for (int off = 32; off > 0; off >>= 1) sq += __shfl_xor(sq, off, 64);
+        __shared__ double red[4];
+        if (lane == 0) red[w] = sq;
+        __syncthreads();
+        if (threadIdx.x == 0) a.partial[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
+    }
+}
+
+int64_t forward_blocks(const GeoK &G) {
+    return (int64_t)G.nviews * ((G.nv + 63) / 64) * ((G.nu + 3) / 4);
+}
+
+void launch_forward(const GeoK &G, int mode, const FwdArgs &a, hipStream_t s) {
+    const int64_t nb = forward_blocks(G);
+    if (nb > 0x7fffffff) throw Error(CBCT_ERR_INVALID, "forward grid too large");
+    dim3 grid((unsigned)nb), block(256);
+    if (mode == FWD_PLAIN)
+        hipLaunchKernelGGL(k_fwd<FWD_PLAIN>, grid, block, 0, s, G, a);
+    else if (mode == FWD_SOLVER)
+        hipLaunchKernelGGL(k_fwd<FWD_SOLVER>, grid, block, 0, s, G, a);
+    else
+        hipLaunchKernelGGL(k_fwd<FWD_COUNT>, grid, block, 0, s, G, a);
+    CBCT_HIP(hipGetLastError());
+}
+
+// ---------------------------------------------------------------- back
+
+__global__ void __launch_bounds__(256)
+k_back(GeoK G, const float *__restrict__ yhat, float *__restrict__ out, const int *brk) {
+    if (brk && *brk == 2) return;
+    extern __shared__ float lds[];
+    const int lane = threadIdx.x & 63;
+    const int w = threadIdx.x >> 6;
+    const int nxb = (G.nx + 3) >> 2;
+    const unsigned b = xcd_remap(blockIdx.x, gridDim.x);
+    const int ib = (int)(b % (unsigned)nxb);
+    const int j = (int)(b / (unsigned)nxb);
+    const int i = ib * 4 + w;
+    const bool colok = i < G.nx;
+    const int ZL = G.nz + 4;
+    float *colb = lds + w * ZL + 2;  // cell k at colb[k], k in [-2, nz+1]
+    for (int t = lane - 2; t < G.nz + 2; t += 64) colb[t] = 0.0f;
+    __syncthreads();
+
+    if (colok) {
+        const float fi = (float)i, fj = (float)j;
+        const float xlo = (fi - 0.5f * G.nx) * G.hx, xhi = xlo + G.hx;
+        const float ylo = (fj - 0.5f * G.ny) * G.hy, yhi = ylo + G.hy;
+        const int nrb = (G.nv + 63) >> 6;
+        for (int view = 0; view < G.nviews; ++view) {
+            const float2 cs = G.trig[view];
+            // detector u range of the column's x-y square (conservative: every
+            // ray meeting the square lands between the extreme corner images)
+            float umin = 3.0e38f, umax = -3.0e38f;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const float X = (q & 1) ? xhi : xlo, Y = (q & 2) ? yhi : ylo;
+                const float depth = G.dso - (X * cs.x + Y * cs.y);
+                const float lat = Y * cs.x - X * cs.y;
+                const float fu = G.dsd * lat / depth / G.du + 0.5f * G.nu - 0.5f;
+                umin = fminf(umin, fu);
+                umax = fmaxf(umax, fu);
+            }
+            const int iu0 = max(0, (int)floorf(umin) - 1);
+            const int iu1 = min(G.nu - 1, (int)ceilf(umax) + 1);
+            for (int iu = iu0; iu <= iu1; ++iu) {
+                const float4 cxy = G.xy[(size_t)view * G.nu + iu];
+                const float ex0 = plane_alpha(fi, cxy.x, cxy.y);
+                const float ex1 = plane_alpha(fi + 1.0f, cxy.x, cxy.y);
+                const float ey0 = plane_alpha(fj, cxy.z, cxy.w);
+                const float ey1 = plane_alpha(fj + 1.0f, cxy.z, cxy.w);
+                const float aa = fmaxf(fminf(ex0, ex1), fminf(ey0, ey1));
+                const float ab = fminf(fmaxf(ex0, ex1), fmaxf(ey0, ey1));
+                if (!(ab > aa)) continue;
+                const float *yrow = yhat + ((size_t)view * G.nu + iu) * G.nv;
+                for (int rb = 0; rb < nrb; ++rb) {
+                    const int iv = rb * 64 + lane;
+                    const bool rok = iv < G.nv;
+                    const int ivc = rok ? iv : G.nv - 1;
+                    const float yv = rok ? yrow[ivc] : 0.0f;
+                    const float4 cz = G.zr[ivc];
+                    int k;
+                    float pe, an;
+                    zlane_init(aa, cz, G.nz, k, pe, an);
+                    const float m = fminf(ab, an);
+                    const float c0 = m - aa;
+                    const float c1 = ab - m;
+                    const int si = cz.w > 0.0f ? 1 : -1;
+                    atomicAdd(&colb[k], c0 * yv);
+                    atomicAdd(&colb[k + si], c1 * yv);
+                }
+            }
+        }
+    }
+    __syncthreads();
+    if (colok) {
+        float *oc = out + ((size_t)j * G.nx + i) * G.Z;
+        for (int t = lane; t < G.Z; t += 64) oc[t] = (t >= 1 && t <= G.nz) ? colb[t - 1] : 0.0f;
+    }
+}
+
+void launch_back(const GeoK &G, const float *yhat, float *out, const int *brk, hipStream_t s) {
+    const int64_t nb = (int64_t)((G.nx + 3) / 4) * G.ny;
+    const size_t shm = sizeof(float) * 4 * (size_t)(G.nz + 4);
+    hipLaunchKernelGGL(k_back, dim3((unsigned)nb), dim3(256), shm, s, G, yhat, out, brk);
+    CBCT_HIP(hipGetLastError());
+}
+
+// ---------------------------------------------------------------- layout kernels
+
+__global__ void __launch_bounds__(256)
+k_transpose(const float *__restrict__ in, float *__restrict__ out, int R, int C, int64_t ib,
+            int64_t ir, int64_t ioff, int64_t ob, int64_t oc, int64_t ooff,
+            const float *__restrict__ Lu2, const float *__restrict__ Lv2) {
+    __shared__ float tile[32][33];
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8
+    const int bc = blockIdx.x, br = blockIdx.y, bb = blockIdx.z;
+    const int64_t ibase = (int64_t)bb * ib + ioff, obase = (int64_t)bb * ob + ooff;
+    for (int q = ty; q < 32; q += 8) {
+        const int r = br * 32 + q, c = bc * 32 + tx;
+        if (r < R && c < C) {
+            float v = in[ibase + (int64_t)r * ir + c];
+            if (Lu2) v *= sqrtf(Lu2[c] + Lv2[r]);
+            tile[q][tx] = v;
+        }
+    }
+    __syncthreads();
+    for (int q = ty; q < 32; q += 8) {
+        const int c = bc * 32 + q, r = br * 32 + tx;
+        if (r < R && c < C) out[obase + (int64_t)c * oc + r] = tile[tx][q];
+    }
+}
+
+void launch_transpose(const float *in, float *out, int B, int R, int C, int64_t ib, int64_t ir,
+                      int64_t ioff, int64_t ob, int64_t oc, int64_t ooff, const float *Lu2,
+                      const float *Lv2, hipStream_t s) {
+    dim3 grid((unsigned)((C + 31) / 32), (unsigned)((R + 31) / 32), (unsigned)B);
+    hipLaunchKernelGGL(k_transpose, grid, dim3(256), 0, s, in, out, R, C, ib, ir, ioff, ob, oc,
+                       ooff, Lu2, Lv2);
+    CBCT_HIP(hipGetLastError());
+}
+
+__global__ void k_fill(float *p, int64_t n, float v) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += stride) p[t] = v;
+}
+
+void launch_fill(float *p, int64_t n, float v, hipStream_t s) {
+    if (n <= 0) return;
+    const int64_t nb = std::min<int64_t>((n + 255) / 256, 65536);
+    hipLaunchKernelGGL(k_fill, dim3((unsigned)nb), dim3(256), 0, s, p, n, v);
+    CBCT_HIP(hipGetLastError());
+}
+
+// x[k][j][i] -> cols (cell (i,j,k) at (j*nx+i)*Z + k + 1): batch j, rows k, cols i.
+void vol_to_cols(const GeoK &G, const float *x, float *cols, hipStream_t s) {
+    launch_transpose(x, cols, G.ny, G.nz, G.nx, G.nx, (int64_t)G.nx * G.ny, 0,
+                     (int64_t)G.nx * G.Z, G.Z, 1, nullptr, nullptr, s);
+}
+
+// cols -> x: batch j, rows i, cols k.
+void cols_to_vol(const GeoK &G, const float *cols, float *x, hipStream_t s) {
+    launch_transpose(cols, x, G.ny, G.nx, G.nz, (int64_t)G.nx * G.Z, G.Z, 1, G.nx,
+                     (int64_t)G.nx * G.ny, 0, nullptr, nullptr, s);
+}
+
+// y[view][v][u] -> ycol[view][u][v] (optionally times L(u, v)): batch view, rows v, cols u.
+void proj_to_cols(const GeoK &G, const float *y, float *ycol, bool scale_by_L, hipStream_t s) {
+    const int64_t per = (int64_t)G.nu * G.nv;
+    launch_transpose(y, ycol, G.nviews, G.nv, G.nu, per, G.nu, 0, per, G.nv, 0,
+                     scale_by_L ? G.Lu2 : nullptr, scale_by_L ? G.Lv2 : nullptr, s);
+}
+
+// ycol[view][u][v] -> y[view][v][u]: batch view, rows u, cols v.
+void cols_to_proj(const GeoK &G, const float *ycol, float *y, hipStream_t s) {
+    const int64_t per = (int64_t)G.nu * G.nv;
+    launch_transpose(ycol, y, G.nviews, G.nu, G.nv, per, G.nv, 0, per, G.nu, 0, nullptr, nullptr,
+                     s);
+}
+
+// ---------------------------------------------------------------- 16-bit operand conversion
+
+__global__ void k_to_f32(const void *in, int dtype, float scale, float *out, int64_t n) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += stride) {
+        float v;
+        if (dtype == CBCT_BF16) {
+            const unsigned short h = ((const unsigned short *)in)[t];
+            v = __uint_as_float((unsigned)h << 16);
+        } else if (dtype == CBCT_F16) {
+            v = (float)((const __half *)in)[t];
+        } else {
+            v = ((const float *)in)[t];
+        }
+        out[t] = v * scale;
+    }
+}
+
+static void to_f32(const void *in, cbct_dtype dt, float scale, float *out, int64_t n,
+                   hipStream_t s) {
+    const int64_t nb = std::min<int64_t>((n + 255) / 256, 65536);
+    hipLaunchKernelGGL(k_to_f32, dim3((unsigned)nb), dim3(256), 0, s, in, (int)dt, scale, out, n);
+    CBCT_HIP(hipGetLastError());
+}
+
+}  // namespace cbct
+
+using namespace cbct;
+
+namespace {
+
+// Stream-ordered temporary device buffer (freed on the same stream).
+struct StreamBuf {
+    void *p = nullptr;
+    hipStream_t s;
+    explicit StreamBuf(size_t bytes, hipStream_t st) : s(st) {
+        if (bytes) CBCT_HIP(hipMallocAsync(&p, bytes, st));
+    }
+    StreamBuf(const StreamBuf &) = delete;
+    StreamBuf &operator=(const StreamBuf &) = delete;
+    ~StreamBuf() {
+        if (p) (void)hipFreeAsync(p, s);
+    }
+    float *f() const { return (float *)p; }
+};
+
+int translate(const std::exception &ex) {
+    if (auto e = dynamic_cast<const Error *>(&ex)) {
+        set_last_error(e->what());
+        return e->code;
+    }
+    set_last_error(ex.what());
+    return CBCT_ERR_INVALID;
+}
+
+void check_dtype(cbct_dtype t, float scale) {
+    CBCT_REQUIRE(t == CBCT_F32 || t == CBCT_BF16 || t == CBCT_F16, "unknown dtype");
+    CBCT_REQUIRE(std::isfinite(scale) && scale > 0.0f, "scale must be finite and > 0");
+}
+
+}  // namespace
+
+extern "C" {
+
+int cbct_forward(const cbct_geom *gc, const void *x, cbct_dtype xt, float x_scale, float *y,
+                 void *hip_stream) {
+    try {
+        clear_last_error();
+        CBCT_REQUIRE(gc && x && y, "null argument");
+        check_dtype(xt, x_scale);
+        cbct_geom *g = const_cast<cbct_geom *>(gc);
+        hipStream_t s = (hipStream_t)hip_stream;
+        GeoK G = geo_for_device(g);
+        const int64_t M = g->n_vox(), N = g->n_proj();
+        StreamBuf cols(sizeof(float) * g->pad_floats(), s);
+        StreamBuf ycol(sizeof(float) * N, s);
+        float *P = cols.f() + kGuard;
+        launch_fill(cols.f(), g->pad_floats(), 0.0f, s);
+        const float *xf = (const float *)x;
+        StreamBuf conv(xt == CBCT_F32 && x_scale == 1.0f ? 0 : sizeof(float) * M, s);
+        if (!(xt == CBCT_F32 && x_scale == 1.0f)) {
+            to_f32(x, xt, x_scale, conv.f(), M, s);
+            xf = conv.f();
+        }
+        vol_to_cols(G, xf, P, s);
+        FwdArgs a{};
+        a.vol = P;
+        a.out = ycol.f();
+        launch_forward(G, FWD_PLAIN, a, s);
+        cols_to_proj(G, ycol.f(), y, s);
+        return CBCT_OK;
+    } catch (const std::exception &e) {
+        return translate(e);
+    }
+}
+
+int cbct_back(const cbct_geom *gc, const void *y, cbct_dtype yt, float y_scale, float *x,
+              void *hip_stream) {
+    try {
+        clear_last_error();
+        CBCT_REQUIRE(gc && x && y, "null argument");
+        check_dtype(yt, y_scale);
+        cbct_geom *g = const_cast<cbct_geom *>(gc);
+        hipStream_t s = (hipStream_t)hip_stream;
+        GeoK G = geo_for_device(g);
+        const int64_t N = g->n_proj();
+        StreamBuf cols(sizeof(float) * g->pad_floats(), s);
+        StreamBuf ycol(sizeof(float) * N, s);
+        const float *yf = (const float *)y;
+        StreamBuf conv(yt == CBCT_F32 && y_scale == 1.0f ? 0 : sizeof(float) * N, s);
+        if (!(yt == CBCT_F32 && y_scale == 1.0f)) {
+            to_f32(y, yt, y_scale, conv.f(), N, s);
+            yf = conv.f();
+        }
+        proj_to_cols(G, yf, ycol.f(), true, s);
+        float *P = cols.f() + kGuard;
+        launch_back(G, ycol.f(), P, nullptr, s);
+        cols_to_vol(G, P, x, s);
+        return CBCT_OK;
+    } catch (const std::exception &e) {
+        return translate(e);
+    }
+}
+
+int cbct_col_sizes(const cbct_geom *gc, int64_t *vol_floats, int64_t *vol_offset,
+                   int64_t *proj_floats) {
+    try {
+        clear_last_error();
+        CBCT_REQUIRE(gc, "null geometry");
+        if (vol_floats) *vol_floats = gc->pad_floats();
+        if (vol_offset) *vol_offset = kGuard;
+        if (proj_floats) *proj_floats = gc->n_proj();
+        return CBCT_OK;
+    } catch (const std::exception &e) {
+        return translate(e);
+    }
+}
+
+int cbct_vol_to_cols(const cbct_geom *gc, const float *x, float *cols, void *hip_stream) {
+    try {
+        clear_last_error();
+        CBCT_REQUIRE(gc && x && cols, "null argument");
+        cbct_geom *g = const_cast<cbct_geom *>(gc);
+        hipStream_t s = (hipStream_t)hip_stream;
+        GeoK G = geo_for_device(g);
+        launch_fill(cols, g->pad_floats(), 0.0f, s);
+        vol_to_cols(G, x, cols + kGuard, s);
+        return CBCT_OK;
+    } catch (const std::exception &e) {
+        return translate(e);
+    }
+}
+
+int cbct_cols_to_vol(const cbct_geom *gc, const float *cols, float *x, void *hip_stream) {
+    try {
+        clear_last_error();
+        CBCT_REQUIRE(gc && x && cols, "null argument");
+        cbct_geom *g = const_cast<cbct_geom *>(gc);
+        GeoK G = geo_for_device(g);
+        cols_to_vol(G, cols + kGuard, x, (hipStream_t)hip_stream);
+        return CBCT_OK;
+    } catch (const std::exception &e) {
+        return translate(e);
+    }
+}
+
+int cbct_proj_to_cols(const cbct_geom *gc, const float *y, float *ycols, int weighted,
+                      void *hip_stream) {
+    try {
+        clear_last_error();
+        CBCT_REQUIRE(gc && y && ycols, "null argument");
+        cbct_geom *g = const_cast<cbct_geom *>(gc);
+        GeoK G = geo_for_device(g);
+        proj_to_cols(G, y, ycols, weighted != 0, (hipStream_t)hip_stream);
+        return CBCT_OK;
+    } catch (const std::exception &e) {
+        return translate(e);
+    }
+}
+
+int cbct_cols_to_proj(const cbct_geom *gc, const float *ycols, float *y, void *hip_stream) {
+    try {
+        clear_last_error();
+        CBCT_REQUIRE(gc && y && ycols, "null argument");
+        cbct_geom *g = const_cast<cbct_geom *>(gc);
+        GeoK G = geo_for_device(g);
+        cols_to_proj(G, ycols, y, (hipStream_t)hip_stream);
+        return CBCT_OK;
+    } catch (const std::exception &e) {
+        return translate(e);
+    }
+}
+
+int cbct_forward_cols(const cbct_geom *gc, const float *cols, float *ycols, void *hip_stream) {
+    try {
+        clear_last_error();
+        CBCT_REQUIRE(gc && cols && ycols, "null argument");
+        cbct_geom *g = const_cast<cbct_geom *>(gc);
+        GeoK G = geo_for_device(g);
+        FwdArgs a{};
+        a.vol = cols + kGuard;
+        a.out = ycols;
+        launch_forward(G, FWD_PLAIN, a, (hipStream_t)hip_stream);
+        return CBCT_OK;
+    } catch (const std::exception &e) {
+        return translate(e);
+    }
+}
+
+int cbct_back_cols(const cbct_geom *gc, const float *ywcols, float *cols, void *hip_stream) {
+    try {
+        clear_last_error();
+        CBCT_REQUIRE(gc && cols && ywcols, "null argument");
+        cbct_geom *g = const_cast<cbct_geom *>(gc);
+        hipStream_t s = (hipStream_t)hip_stream;
+        GeoK G = geo_for_device(g);
+        // guards are outside every column the kernel writes
+        launch_fill(cols, kGuard, 0.0f, s);
+        launch_fill(cols + kGuard + g->n_col() * G.Z, kGuard, 0.0f, s);
+        launch_back(G, ywcols, cols + kGuard, nullptr, s);
+        return CBCT_OK;
+    } catch (const std::exception &e) {
+        return translate(e);
+    }
+}
+
+int cbct_geom_nnz(const cbct_geom *gc, int64_t *nnz, void *hip_stream) {
+    try {
+        clear_last_error();
+        CBCT_REQUIRE(gc && nnz, "null argument");
+        cbct_geom *g = const_cast<cbct_geom *>(gc);
+        hipStream_t s = (hipStream_t)hip_stream;
+        GeoK G = geo_for_device(g);
+        StreamBuf cols(sizeof(float) * g->pad_floats(), s);
+        StreamBuf cnt(sizeof(unsigned long long), s);
+        CBCT_HIP(hipMemsetAsync(cnt.p, 0, sizeof(unsigned long long), s));
+        launch_fill(cols.f(), g->pad_floats(), 0.0f, s);
+        FwdArgs a{};
+        a.vol = cols.f() + kGuard;
+        a.count = (unsigned long long *)cnt.p;
+        launch_forward(G, FWD_COUNT, a, s);
+        unsigned long long h = 0;
+        CBCT_HIP(hipMemcpyAsync(&h, cnt.p, sizeof(h), hipMemcpyDeviceToHost, s));
+        CBCT_HIP(hipStreamSynchronize(s));
+        *nnz = (int64_t)h;
+        return CBCT_OK;
+    } catch (const std::exception &e) {
+        return translate(e);
+    }
+}
+
+}  // extern "C"
