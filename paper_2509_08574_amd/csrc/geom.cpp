@@ -93,6 +93,18 @@ static void validate(const cbct_geom_desc *d) {
             CBCT_REQUIRE(std::isfinite(d->angles[v]), "non-finite view angle");
 }
 
+static GeoK make_geok(const cbct_geom *g, const DevTables &t) {
+    const cbct_geom_desc &d = g->d;
+    GeoK G;
+    G.nx = d.nx; G.ny = d.ny; G.nz = d.nz; G.nu = d.nu; G.nv = d.nv; G.nviews = d.n_views;
+    G.Z = d.nz + 2;
+    G.hx = (float)d.vx; G.hy = (float)d.vy; G.hz = (float)d.vz;
+    G.dso = (float)d.dso; G.dsd = (float)d.dsd; G.du = (float)d.du; G.dv = (float)d.dv;
+    G.xy = t.xy; G.zr = t.zr; G.Lu2 = t.Lu2; G.Lv2 = t.Lv2; G.trig = t.trig;
+    G.seghdr = t.seghdr; G.seg = t.seg; G.seg_stride = d.nx + d.ny + 2;
+    return G;
+}
+
 GeoK geo_for_device(cbct_geom *g) {
     int dev = 0;
     CBCT_HIP(hipGetDevice(&dev));
@@ -118,9 +130,16 @@ GeoK geo_for_device(cbct_geom *g) {
                                    hipMemcpyHostToDevice));
                 CBCT_HIP(hipMemcpy(t.trig, g->trig.data(), sizeof(float2) * g->trig.size(),
                                    hipMemcpyHostToDevice));
+                const size_t nr = (size_t)d.n_views * d.nu;
+                const size_t stride = (size_t)d.nx + d.ny + 2;
+                CBCT_HIP(hipMalloc(&t.seghdr, sizeof(int2) * nr));
+                CBCT_HIP(hipMalloc(&t.seg, sizeof(int2) * nr * stride));
+                GeoK G = make_geok(g, t);
+                build_segment_tables(G, t.seghdr, t.seg);
             } catch (...) {
                 (void)hipFree(t.xy); (void)hipFree(t.zr); (void)hipFree(t.Lu2);
-                (void)hipFree(t.Lv2); (void)hipFree(t.trig);
+                (void)hipFree(t.Lv2); (void)hipFree(t.trig); (void)hipFree(t.seghdr);
+                (void)hipFree(t.seg);
                 throw;
             }
             g->dev[dev] = t;
@@ -128,14 +147,14 @@ GeoK geo_for_device(cbct_geom *g) {
             t = it->second;
         }
     }
-    const cbct_geom_desc &d = g->d;
-    GeoK G;
-    G.nx = d.nx; G.ny = d.ny; G.nz = d.nz; G.nu = d.nu; G.nv = d.nv; G.nviews = d.n_views;
-    G.Z = d.nz + 2;
-    G.hx = (float)d.vx; G.hy = (float)d.vy;
-    G.dso = (float)d.dso; G.dsd = (float)d.dsd; G.du = (float)d.du; G.dv = (float)d.dv;
-    G.xy = t.xy; G.zr = t.zr; G.Lu2 = t.Lu2; G.Lv2 = t.Lv2; G.trig = t.trig;
-    return G;
+    return make_geok(g, t);
+}
+
+size_t geom_table_bytes(const cbct_geom_desc &d) {
+    const size_t nr = (size_t)d.n_views * d.nu;
+    return nr * (sizeof(float4) + sizeof(int2) * (1 + (size_t)d.nx + d.ny + 2)) +
+           (size_t)d.nv * (sizeof(float4) + sizeof(float)) + (size_t)d.nu * sizeof(float) +
+           (size_t)d.n_views * sizeof(float2);
 }
 
 }  // namespace cbct
@@ -184,6 +203,8 @@ void cbct_geom_destroy(cbct_geom *g) {
         (void)hipFree(kv.second.Lu2);
         (void)hipFree(kv.second.Lv2);
         (void)hipFree(kv.second.trig);
+        (void)hipFree(kv.second.seghdr);
+        (void)hipFree(kv.second.seg);
     }
     (void)hipSetDevice(cur);
     delete g;

@@ -50,13 +50,22 @@ constexpr int kGuard = 64;
 struct GeoK {
     int nx, ny, nz, nu, nv, nviews;
     int Z;               // nz + 2
-    float hx, hy;        // voxel size in x, y [mm] (detector footprint only)
+    float hx, hy, hz;    // voxel size [mm] (detector footprints and row ranges only)
     float dso, dsd, du, dv;
     const float4 *xy;    // [nviews*nu]: (xi0, rx, eta0, ry) -- see geom.cpp
     const float4 *zr;    // [nv]: (z0, rg, dz, s)
     const float *Lu2;    // [nu]: dsd^2 + u^2
     const float *Lv2;    // [nv]: v^2
     const float2 *trig;  // [nviews]: (cos th, sin th)
+    // x-y traversal of every detector column (view, iu), precomputed on the
+    // device with the same float32 operations the kernels would use:
+    // seghdr[r] = (a_in as float bits, number of segments n), and
+    // seg[r*seg_stride + q] = (exit parameter ab as float bits, column j*nx + i)
+    // for q < n, followed by one dummy entry (column 0) so that a kernel may
+    // prefetch one entry past the end.
+    const int2 *seghdr;  // [nviews*nu]
+    const int2 *seg;     // [nviews*nu*seg_stride]
+    int seg_stride;      // nx + ny + 2
 };
 
 struct DevTables {
@@ -65,6 +74,8 @@ struct DevTables {
     float *Lu2 = nullptr;
     float *Lv2 = nullptr;
     float2 *trig = nullptr;
+    int2 *seghdr = nullptr;
+    int2 *seg = nullptr;
 };
 
 }  // namespace cbct
@@ -90,8 +101,13 @@ struct cbct_geom {
 
 namespace cbct {
 
-// Kernel arguments for geometry g on the current device (uploads tables once).
+// Kernel arguments for geometry g on the current device (uploads tables and
+// builds the segment tables once per device).
 GeoK geo_for_device(cbct_geom *g);
+// Builds the x-y segment tables of G (seghdr/seg must be allocated); synchronous.
+void build_segment_tables(const GeoK &G, int2 *seghdr, int2 *seg);
+// Bytes of device memory held per device by the geometry's tables.
+size_t geom_table_bytes(const cbct_geom_desc &d);
 
 // ---- projector launchers (proj.hip) ----
 // Forward epilogue modes.

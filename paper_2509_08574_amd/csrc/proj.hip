@@ -27,71 +27,33 @@
 
 namespace cbct {
 
-// ---------------------------------------------------------------- forward
+// ---------------------------------------------------------------- segment tables
 
-template <int MODE>
+// One thread per detector column (view, iu): the x-y traversal shared by all
+// rows of that column.  The sequence of (exit parameter, voxel column) is
+// exactly what k_fwd would compute on the fly, and the same values k_back
+// recomputes per column from the four bounding planes.
 __global__ void __launch_bounds__(256)
-k_fwd(GeoK G, FwdArgs a) {
-    if constexpr (MODE == FWD_SOLVER) {
-        if (*a.brk == 2) return;
-    }
-    const int lane = threadIdx.x & 63;
-    const int w = threadIdx.x >> 6;
-    const int nub = (G.nu + 3) >> 2, nrb = (G.nv + 63) >> 6;
-    const unsigned b = xcd_remap(blockIdx.x, gridDim.x);
-    const int ub = (int)(b % (unsigned)nub);
-    const unsigned t = b / (unsigned)nub;
-    const int rb = (int)(t % (unsigned)nrb);
-    const int view = (int)(t / (unsigned)nrb);
-    const int iu = ub * 4 + w, iv = rb * 64 + lane;
-    const int iuc = iu < G.nu ? iu : G.nu - 1;
-    const int ivc = iv < G.nv ? iv : G.nv - 1;
-
-    const float4 cxy = G.xy[(size_t)view * G.nu + iuc];
-    const float4 cz = G.zr[ivc];
+k_segtab(GeoK G, int2 *__restrict__ seghdr, int2 *__restrict__ seg) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= G.nviews * G.nu) return;
+    const float4 cxy = G.xy[r];
     const float ax0 = plane_alpha(0.0f, cxy.x, cxy.y), axN = plane_alpha((float)G.nx, cxy.x, cxy.y);
     const float ay0 = plane_alpha(0.0f, cxy.z, cxy.w), ayN = plane_alpha((float)G.ny, cxy.z, cxy.w);
     const float a_in = fmaxf(fminf(ax0, axN), fminf(ay0, ayN));
     const float a_out = fminf(fmaxf(ax0, axN), fmaxf(ay0, ayN));
-
-    float acc = 0.0f;
-    unsigned cnt = 0;
+    int2 *out = seg + (size_t)r * G.seg_stride;
+    int n = 0;
     if (a_out > a_in) {
         const int sx = cxy.y > 0.0f ? 1 : -1, sy = cxy.w > 0.0f ? 1 : -1;
         int i = xy_cell(a_in, cxy.x, cxy.y, G.nx);
         int j = xy_cell(a_in, cxy.z, cxy.w, G.ny);
         float axn = plane_alpha((float)(i + (sx > 0)), cxy.x, cxy.y);
         float ayn = plane_alpha((float)(j + (sy > 0)), cxy.z, cxy.w);
-        float aa = a_in;
-        int k;
-        float pe, an;
-        zlane_init(aa, cz, G.nz, k, pe, an);
-        const float s = cz.w;
-        const int si = s > 0.0f ? 1 : -1;
-        int kk = k + 1;  // local index in the padded column
-        const int kmax = G.nz + 1;
-        const int nit = G.nx + G.ny + 2;
-        for (int it = 0; it < nit; ++it) {
+        const int nmax = G.seg_stride - 1;
+        while (n < nmax) {
             const float ab = fminf(axn, ayn);
-            const int col = __builtin_amdgcn_readfirstlane(j * G.nx + i);
-            const float *colp = a.vol + (size_t)col * G.Z;
-            const float m = fminf(ab, an);
-            const float c0 = m - aa;
-            const float c1 = ab - m;
-            const float v0 = colp[kk];
-            const float v1 = colp[kk + si];
-            if constexpr (MODE == FWD_COUNT) {
-                cnt += (c0 > 0.0f && kk >= 1 && kk <= G.nz) ? 1u : 0u;
-                cnt += (c1 > 0.0f && kk + si >= 1 && kk + si <= G.nz) ? 1u : 0u;
-            } else {
-                acc = fmaf(c0, v0, acc);
-                acc = fmaf(c1, v1, acc);
-            }
-            if (an < ab) {
-                pe += s;
-                an = plane_alpha(pe, cz.x, cz.y);
-                kk = min(max(kk + si, 0), kmax);
-            }
+            out[n++] = make_int2(__float_as_int(ab), j * G.nx + i);
             const bool adx = axn == ab, ady = ayn == ab;
             if (adx) {
                 i += sx;
@@ -102,6 +64,96 @@ k_fwd(GeoK G, FwdArgs a) {
                 ayn = plane_alpha((float)(j + (sy > 0)), cxy.z, cxy.w);
             }
             if ((unsigned)i >= (unsigned)G.nx || (unsigned)j >= (unsigned)G.ny) break;
+        }
+    }
+    out[n] = make_int2(__float_as_int(a_in), 0);  // dummy entry for one-ahead prefetch
+    seghdr[r] = make_int2(__float_as_int(a_in), n);
+}
+
+void build_segment_tables(const GeoK &G, int2 *seghdr, int2 *seg) {
+    hipStream_t s;
+    CBCT_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+    const int nr = G.nviews * G.nu;
+    hipLaunchKernelGGL(k_segtab, dim3((unsigned)((nr + 255) / 256)), dim3(256), 0, s, G, seghdr,
+                       seg);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    (void)hipStreamDestroy(s);
+    CBCT_HIP(e);
+}
+
+// ---------------------------------------------------------------- forward
+
+// Column `col`'s cell (local index) `q` as an unsigned byte offset from the
+// uniform base `colm` (= column start - 1 cell), so the compiler can use the
+// scalar-base + 32-bit vector-offset load form.
+__device__ __forceinline__ float ld_cell(const float *colm, unsigned q) {
+    return *(const float *)((const char *)colm + (q << 2));
+}
+
+template <int MODE>
+__global__ void __launch_bounds__(256)
+k_fwd(GeoK G, FwdArgs a) {
+    if constexpr (MODE == FWD_SOLVER) {
+        if (*a.brk == 2) return;
+    }
+    const int lane = threadIdx.x & 63;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int nub = (G.nu + 3) >> 2, nrb = (G.nv + 63) >> 6;
+    const unsigned b = xcd_remap(blockIdx.x, gridDim.x);
+    const int ub = (int)(b % (unsigned)nub);
+    const unsigned t = b / (unsigned)nub;
+    const int rb = (int)(t % (unsigned)nrb);
+    const int view = (int)(t / (unsigned)nrb);
+    const int iu = ub * 4 + w, iv = rb * 64 + lane;
+    const int iuc = iu < G.nu ? iu : G.nu - 1;
+    const int ivc = iv < G.nv ? iv : G.nv - 1;
+
+    const int r = view * G.nu + iuc;              // wave-uniform
+    const int2 hdr = G.seghdr[r];
+    const int nseg = hdr.y;
+    const int2 *sp = G.seg + (size_t)r * G.seg_stride;
+    const float4 cz = G.zr[ivc];
+
+    float acc = 0.0f;
+    unsigned cnt = 0;
+    if (nseg > 0) {
+        float aa = __int_as_float(hdr.x);
+        int k;
+        float pe, an;
+        zlane_init(aa, cz, G.nz, k, pe, an);
+        const float s = cz.w;
+        const int si = s > 0.0f ? 1 : -1;
+        unsigned q = (unsigned)(k + 2);   // local cell index + 1 (>= 1)
+        const unsigned qmax = (unsigned)G.nz + 2;
+        const float *vol_m = a.vol - 1;
+        int2 sg = sp[0];
+        const float *colm = vol_m + (size_t)sg.y * G.Z;
+        float v0 = ld_cell(colm, q), v1 = ld_cell(colm, q + si);
+        for (int n = 0; n < nseg; ++n) {
+            const float ab = __int_as_float(sg.x);
+            const float m = fminf(ab, an);
+            const float c0 = m - aa;
+            const float c1 = ab - m;
+            const unsigned qc = q;  // cells of this segment: qc and qc + si
+            if (an < ab) {
+                pe += s;
+                an = plane_alpha(pe, cz.x, cz.y);
+                q = min(max(q + si, 1u), qmax);
+            }
+            // next segment's column and cells (one-ahead loads; entry nseg is a dummy)
+            sg = sp[n + 1];
+            colm = vol_m + (size_t)sg.y * G.Z;
+            const float v0n = ld_cell(colm, q), v1n = ld_cell(colm, q + si);
+            if constexpr (MODE == FWD_COUNT) {
+                cnt += (c0 > 0.0f && qc >= 2 && qc <= (unsigned)G.nz + 1) ? 1u : 0u;
+                cnt += (c1 > 0.0f && qc + si >= 2 && qc + si <= (unsigned)G.nz + 1) ? 1u : 0u;
+            } else {
+                acc = fmaf(c0, v0, acc);
+                acc = fmaf(c1, v1, acc);
+            }
+            v0 = v0n;
+            v1 = v1n;
             aa = ab;
         }
     }
@@ -153,84 +205,144 @@ void launch_forward(const GeoK &G, int mode, const FwdArgs &a, hipStream_t s) {
 
 // ---------------------------------------------------------------- back
 
+// Gather form of A^T.  One wave owns one voxel column (i, j) and a block of up to
+// 64*NQ cells; lane l accumulates cells k = k0 + l + 64 q.  For every view, the
+// detector columns u whose rays cross (i, j) give the column interval [aa, ab]
+// (same float32 operations as the forward traversal); the rows that can meet
+// cell k are those whose height z = (a_ref + a') v lies in the cell for some a'
+// in [aa, ab], a range that follows from two divisions.  Each candidate row's
+// chord is the overlap of [aa, ab] with the cell's own z-plane interval,
+//     c = max(0, min(ab, max(zA, zB)) - max(aa, min(zA, zB))),
+// zA, zB = (k - z0) rg, (k + 1 - z0) rg.  Because the forward kernel's cell
+// state satisfies entry(k) < aa <= exit(k) at every segment start and meets at
+// most one z plane per segment, this equals its c0 / c1 bit for bit, and is 0
+// for every cell the forward does not touch: the two kernels apply the same
+// matrix.  No atomics; every cell is summed in a fixed order.
+template <int NQ>
 __global__ void __launch_bounds__(256)
-k_back(GeoK G, const float *__restrict__ yhat, float *__restrict__ out, const int *brk) {
+k_back(GeoK G, const float *__restrict__ yhat, float *__restrict__ out, const int *brk,
+       float a_ref, float z_lo_mm, float hz, int kspan) {
     if (brk && *brk == 2) return;
     extern __shared__ float lds[];
-    const int lane = threadIdx.x & 63;
-    const int w = threadIdx.x >> 6;
-    const int nxb = (G.nx + 3) >> 2;
-    const unsigned b = xcd_remap(blockIdx.x, gridDim.x);
-    const int ib = (int)(b % (unsigned)nxb);
-    const int j = (int)(b / (unsigned)nxb);
-    const int i = ib * 4 + w;
-    const bool colok = i < G.nx;
-    const int ZL = G.nz + 4;
-    float *colb = lds + w * ZL + 2;  // cell k at colb[k], k in [-2, nz+1]
-    for (int t = lane - 2; t < G.nz + 2; t += 64) colb[t] = 0.0f;
+    float2 *zrs = (float2 *)lds;  // per-row (z0, rg)
+    for (int t = threadIdx.x; t < G.nv; t += 256) {
+        const float4 z = G.zr[t];
+        zrs[t] = make_float2(z.x, z.y);
+    }
     __syncthreads();
 
-    if (colok) {
-        const float fi = (float)i, fj = (float)j;
-        const float xlo = (fi - 0.5f * G.nx) * G.hx, xhi = xlo + G.hx;
-        const float ylo = (fj - 0.5f * G.ny) * G.hy, yhi = ylo + G.hy;
-        const int nrb = (G.nv + 63) >> 6;
-        for (int view = 0; view < G.nviews; ++view) {
-            const float2 cs = G.trig[view];
-            // detector u range of the column's x-y square (conservative: every
-            // ray meeting the square lands between the extreme corner images)
-            float umin = 3.0e38f, umax = -3.0e38f;
+    const int lane = threadIdx.x & 63;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int nzs = (G.nz + kspan - 1) / kspan;        // z splits per column
+    const int64_t lw = (int64_t)xcd_remap(blockIdx.x, gridDim.x) * 4 + w;
+    const int64_t col = lw / nzs;
+    const int zs = (int)(lw % nzs);
+    if (col >= (int64_t)G.nx * G.ny) return;
+    const int i = (int)(col % G.nx), j = (int)(col / G.nx);
+    const int kbase = zs * kspan;
+
+    float acc[NQ], fk[NQ], zk0[NQ], zk1[NQ];
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const float X = (q & 1) ? xhi : xlo, Y = (q & 2) ? yhi : ylo;
-                const float depth = G.dso - (X * cs.x + Y * cs.y);
-                const float lat = Y * cs.x - X * cs.y;
-                const float fu = G.dsd * lat / depth / G.du + 0.5f * G.nu - 0.5f;
-                umin = fminf(umin, fu);
-                umax = fmaxf(umax, fu);
-            }
-            const int iu0 = max(0, (int)floorf(umin) - 1);
-            const int iu1 = min(G.nu - 1, (int)ceilf(umax) + 1);
-            for (int iu = iu0; iu <= iu1; ++iu) {
-                const float4 cxy = G.xy[(size_t)view * G.nu + iu];
-                const float ex0 = plane_alpha(fi, cxy.x, cxy.y);
-                const float ex1 = plane_alpha(fi + 1.0f, cxy.x, cxy.y);
-                const float ey0 = plane_alpha(fj, cxy.z, cxy.w);
-                const float ey1 = plane_alpha(fj + 1.0f, cxy.z, cxy.w);
-                const float aa = fmaxf(fminf(ex0, ex1), fminf(ey0, ey1));
-                const float ab = fminf(fmaxf(ex0, ex1), fmaxf(ey0, ey1));
-                if (!(ab > aa)) continue;
-                const float *yrow = yhat + ((size_t)view * G.nu + iu) * G.nv;
-                for (int rb = 0; rb < nrb; ++rb) {
-                    const int iv = rb * 64 + lane;
-                    const bool rok = iv < G.nv;
-                    const int ivc = rok ? iv : G.nv - 1;
-                    const float yv = rok ? yrow[ivc] : 0.0f;
-                    const float4 cz = G.zr[ivc];
-                    int k;
-                    float pe, an;
-                    zlane_init(aa, cz, G.nz, k, pe, an);
-                    const float m = fminf(ab, an);
-                    const float c0 = m - aa;
-                    const float c1 = ab - m;
-                    const int si = cz.w > 0.0f ? 1 : -1;
-                    atomicAdd(&colb[k], c0 * yv);
-                    atomicAdd(&colb[k + si], c1 * yv);
+    for (int q = 0; q < NQ; ++q) {
+        acc[q] = 0.0f;
+        fk[q] = (float)(kbase + lane + 64 * q);
+        zk0[q] = fmaf(fk[q], hz, z_lo_mm);   // cell's lower and upper z [mm]
+        zk1[q] = zk0[q] + hz;
+    }
+    const float fi = (float)i, fj = (float)j;
+    const float xlo = (fi - 0.5f * G.nx) * G.hx, xhi = xlo + G.hx;
+    const float ylo = (fj - 0.5f * G.ny) * G.hy, yhi = ylo + G.hy;
+    const float fu_scale = G.dsd / G.du, fu_off = 0.5f * G.nu - 0.5f;
+    const float idv = 1.0f / G.dv, fv_off = 0.5f * G.nv - 0.5f;
+    const float rmax = (float)(G.nv - 1);
+
+    for (int view = 0; view < G.nviews; ++view) {
+        const float2 cs = G.trig[view];
+        // detector u range of the column's x-y square (conservative: every ray
+        // meeting the square lands between the extreme corner images; the
+        // one-pixel margin covers the approximate reciprocal)
+        float umin = 3.0e38f, umax = -3.0e38f;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const float X = (c & 1) ? xhi : xlo, Y = (c & 2) ? yhi : ylo;
+            const float depth = G.dso - (X * cs.x + Y * cs.y);
+            const float lat = Y * cs.x - X * cs.y;
+            const float fu = fmaf(lat * __builtin_amdgcn_rcpf(depth), fu_scale, fu_off);
+            umin = fminf(umin, fu);
+            umax = fmaxf(umax, fu);
+        }
+        const int iu0 = max(0, (int)floorf(umin) - 1);
+        const int iu1 = min(G.nu - 1, (int)ceilf(umax) + 1);
+        for (int iu = iu0; iu <= iu1; ++iu) {
+            const float4 cxy = G.xy[(size_t)view * G.nu + iu];
+            const float ex0 = plane_alpha(fi, cxy.x, cxy.y);
+            const float ex1 = plane_alpha(fi + 1.0f, cxy.x, cxy.y);
+            const float ey0 = plane_alpha(fj, cxy.z, cxy.w);
+            const float ey1 = plane_alpha(fj + 1.0f, cxy.z, cxy.w);
+            const float aa = fmaxf(fminf(ex0, ex1), fminf(ey0, ey1));
+            const float ab = fminf(fmaxf(ex0, ex1), fmaxf(ey0, ey1));
+            if (!(ab > aa)) continue;
+            // heights reached by row v over the interval: z = A v, A in [A1, A2]
+            const float iA1 = __builtin_amdgcn_rcpf(a_ref + aa) * idv;
+            const float iA2 = __builtin_amdgcn_rcpf(a_ref + ab) * idv;
+            const float *yrow = yhat + ((size_t)view * G.nu + iu) * G.nv;
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) {
+                // rows whose centre v satisfies z_k <= A v <= z_k+1 for some A
+                const float flo = fmaf(zk0[q], zk0[q] >= 0.0f ? iA2 : iA1, fv_off);
+                const float fhi = fmaf(zk1[q], zk1[q] >= 0.0f ? iA1 : iA2, fv_off);
+                const float rlo = fmaxf(ceilf(flo - 1e-3f), 0.0f);
+                const float rhi = fminf(floorf(fhi + 1e-3f), rmax);
+                int r = (int)rlo;
+                const int r1 = fk[q] < (float)G.nz ? (int)rhi : -1;
+                float a = acc[q];
+                for (; r <= r1; ++r) {
+                    const float2 z = zrs[r];
+                    const float zA = (fk[q] - z.x) * z.y;
+                    const float zB = (fk[q] + 1.0f - z.x) * z.y;
+                    const float lo = fmaxf(aa, fminf(zA, zB));
+                    const float hi = fminf(ab, fmaxf(zA, zB));
+                    a = fmaf(fmaxf(hi - lo, 0.0f), yrow[r], a);
                 }
+                acc[q] = a;
             }
         }
     }
-    __syncthreads();
-    if (colok) {
-        float *oc = out + ((size_t)j * G.nx + i) * G.Z;
-        for (int t = lane; t < G.Z; t += 64) oc[t] = (t >= 1 && t <= G.nz) ? colb[t - 1] : 0.0f;
+    float *oc = out + (size_t)col * G.Z;
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        const int k = kbase + lane + 64 * q;
+        if (k < G.nz && k < kbase + kspan) oc[k + 1] = acc[q];
     }
+    if (zs == 0 && lane == 0) oc[0] = 0.0f;
+    if (zs == nzs - 1 && lane == 0) oc[G.nz + 1] = 0.0f;
 }
 
 void launch_back(const GeoK &G, const float *yhat, float *out, const int *brk, hipStream_t s) {
-    const int64_t nb = (int64_t)((G.nx + 3) / 4) * G.ny;
-    const size_t shm = sizeof(float) * 4 * (size_t)(G.nz + 4);
-    hipLaunchKernelGGL(k_back, dim3((unsigned)nb), dim3(256), shm, s, G, yhat, out, brk);
+    // cells per wave: 64 * NQ, NQ <= 8; columns taller than 512 cells are split
+    const int nq = std::min(8, (G.nz + 63) / 64);
+    const int kspan = 64 * nq;
+    const int nzs = (G.nz + kspan - 1) / kspan;
+    const int64_t nwaves = (int64_t)G.nx * G.ny * nzs;
+    const int64_t nb = (nwaves + 3) / 4;
+    if (nb > 0x7fffffff) throw Error(CBCT_ERR_INVALID, "back grid too large");
+    const size_t shm = sizeof(float2) * (size_t)G.nv;
+    const float a_ref = G.dso / G.dsd;
+    const float z_lo_mm = -0.5f * G.nz * G.hz;
+    auto go = [&](auto kern) {
+        hipLaunchKernelGGL(kern, dim3((unsigned)nb), dim3(256), shm, s, G, yhat, out, brk, a_ref,
+                           z_lo_mm, G.hz, kspan);
+    };
+    switch (nq) {
+        case 1: go(k_back<1>); break;
+        case 2: go(k_back<2>); break;
+        case 3: go(k_back<3>); break;
+        case 4: go(k_back<4>); break;
+        case 5: go(k_back<5>); break;
+        case 6: go(k_back<6>); break;
+        case 7: go(k_back<7>); break;
+        default: go(k_back<8>); break;
+    }
     CBCT_HIP(hipGetLastError());
 }
 
