@@ -40,6 +40,8 @@ def main():
                     help="prior image: 720-view plain-LSQR reconstruction, or the true base object")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--op-reps", type=int, default=10)
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="also run one plain device copy of this many MiB (profiler calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
@@ -60,6 +62,14 @@ def main():
     g = cbct.Geometry.from_dict(gd)
     M, N = g.sizes()
     V = gd["n_views"]
+
+    if args.calib_copy_mib > 0:
+        n = args.calib_copy_mib * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     # ---------------- inputs (not timed)
     t0 = time.time()

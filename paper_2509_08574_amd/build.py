@@ -22,10 +22,15 @@ FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-ffp-contract=
          "-Wall", "-Wno-unused-command-line-argument", f"-I{INCLUDE}"]
 
 
+# The projector kernels never see NaN (all plane parameters are finite by
+# construction), so min/max need no NaN canonicalisation there.
+PER_FILE = {"proj.hip": ["-fno-honor-nans"]}
+
+
 def _compile(src: str, outdir: str, verbose: bool) -> str:
     obj = os.path.join(outdir, os.path.splitext(src)[0] + ".o")
     lang = ["-x", "hip"] if src.endswith(".hip") else []
-    cmd = [HIPCC, *FLAGS, *lang, "-c", os.path.join(CSRC, src), "-o", obj]
+    cmd = [HIPCC, *FLAGS, *PER_FILE.get(src, []), *lang, "-c", os.path.join(CSRC, src), "-o", obj]
     if verbose:
         print(" ".join(cmd), file=sys.stderr)
     r = subprocess.run(cmd, capture_output=True, text=True)

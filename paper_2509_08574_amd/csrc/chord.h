@@ -11,9 +11,10 @@
 // resolution than alpha itself).
 //
 // Plane crossings.  In voxel-index units the ray's x position is
-// xi(a') = xi0 + a' / rx, so x-plane p (p = 0..nx) is crossed at
-// a' = (p - xi0) * rx; likewise for y (eta0, ry) and z (z0, rg).  Coefficients
-// come from per-(view, u) and per-row tables computed in float64 on the host.
+// xi(a') = xi0 + a' * dxi, so x-plane p (p = 0..nx) is crossed at
+// a' = (p - xi0) / dxi = fma(p, rx, cx) with rx = 1/dxi and cx = -xi0/dxi
+// rounded once from float64 on the host; likewise for y (ry, cy) and z
+// (rg, cz).  Coefficients come from per-(view, u) and per-row tables.
 //
 // Rays are traversed column by column (a column = all z cells of one (i, j)):
 // every ray of one detector column u crosses the same sequence of (i, j)
@@ -30,12 +31,12 @@
 
 namespace cbct {
 
-__device__ __forceinline__ float plane_alpha(float p, float c0, float r) { return (p - c0) * r; }
+__device__ __forceinline__ float plane_alpha(float p, float r, float c) { return fmaf(p, r, c); }
 
 // Cell of the x (or y) grid that contains the ray at parameter a, i.e. the
 // cell whose entry plane is crossed at or before a and whose exit plane after
-// a; clamped to [0, n-1].
-__device__ __forceinline__ int xy_cell(float a, float c0, float r, int n) {
+// a; clamped to [0, n-1].  c0 is the index position at a' = 0 (guess only).
+__device__ __forceinline__ int xy_cell(float a, float c0, float r, float c, int n) {
     const float d = 1.0f / r;
     float t = floorf(fmaf(a, d, c0));
     t = fminf(fmaxf(t, 0.0f), (float)(n - 1));
@@ -44,9 +45,9 @@ __device__ __forceinline__ int xy_cell(float a, float c0, float r, int n) {
 #pragma unroll
     for (int it = 0; it < 2; ++it) {
         const float tn = t + s;
-        if (!(plane_alpha(t + up, c0, r) > a) && tn >= 0.0f && tn <= (float)(n - 1)) t = tn;
+        if (!(plane_alpha(t + up, r, c) > a) && tn >= 0.0f && tn <= (float)(n - 1)) t = tn;
         const float tp = t - s;
-        if (plane_alpha(t + 1.0f - up, c0, r) > a && tp >= 0.0f && tp <= (float)(n - 1)) t = tp;
+        if (plane_alpha(t + 1.0f - up, r, c) > a && tp >= 0.0f && tp <= (float)(n - 1)) t = tp;
     }
     return (int)t;
 }
@@ -57,17 +58,19 @@ __device__ __forceinline__ int xy_cell(float a, float c0, float r, int n) {
 // A ray outside the z range sits in the pad cell on its side: below the volume
 // moving up it is in cell -1 whose exit plane is 0 (and symmetrically above),
 // so it enters the volume exactly at the boundary plane.
+// zr = (z0, rg, cz, dz) for the ray's detector row.
 __device__ __forceinline__ void zlane_init(float a, float4 zr, int nz, int &k, float &pe,
                                            float &an) {
-    const float z0 = zr.x, rg = zr.y, dz = zr.z, s = zr.w;
-    const float up = s > 0.0f ? 1.0f : 0.0f;
+    const float z0 = zr.x, rg = zr.y, cz = zr.z, dz = zr.w;
+    const float up = rg > 0.0f ? 1.0f : 0.0f;
+    const float s = rg > 0.0f ? 1.0f : -1.0f;
     float kt = floorf(fmaf(a, dz, z0));
-    if (!(plane_alpha(kt + up, z0, rg) >= a)) kt += s;
-    if (!(plane_alpha(kt + 1.0f - up, z0, rg) < a)) kt -= s;
+    if (!(plane_alpha(kt + up, rg, cz) >= a)) kt += s;
+    if (!(plane_alpha(kt + 1.0f - up, rg, cz) < a)) kt -= s;
     kt = fminf(fmaxf(kt, -1.0f), (float)nz);
     k = (int)kt;
     pe = kt + up;
-    an = plane_alpha(pe, z0, rg);
+    an = plane_alpha(pe, rg, cz);
 }
 
 // Block id remap for the 8 XCDs of MI355X: the dispatcher hands consecutive

@@ -11,18 +11,27 @@ static thread_local std::string g_last_error;
 void set_last_error(const std::string &msg) { g_last_error = msg; }
 void clear_last_error() { g_last_error.clear(); }
 
-// Coefficients (c0, r) of one axis of a ray written as
-//   index position(a') = c0 + a' / r,  a' = alpha - a_ref,
+// Coefficients of one axis of a ray written as
+//   index position(a') = c0 + a' * dpos,  a' = alpha - a_ref,
 // from the source coordinate S, direction component d (P - S) and the grid's
-// low edge lo and cell size h.  Plane p is crossed at a' = (p - c0) * r.
+// low edge lo and cell size h.  Plane p is crossed at a' = (p - c0) / dpos,
+// evaluated by the kernels as fma(p, r, c) with r = 1/dpos and c = -c0/dpos
+// rounded once from float64.
 static void axis_coeffs(double S, double d, double lo, double h, double a_ref, float &c0,
-                        float &r) {
+                        float &r, float &c, float &dpos_f) {
     const double dpos = d / h;                     // index units per unit alpha
     const double pos_ref = (S - lo) / h + a_ref * dpos;  // index position at a' = 0
     c0 = (float)pos_ref;
-    // A ray parallel to the planes never crosses them: a huge finite slope keeps
-    // (p - c0) * r finite and far outside any traversal interval.
-    r = std::fabs(dpos) > 1e-30 ? (float)(1.0 / dpos) : 1e30f;
+    dpos_f = (float)dpos;
+    if (std::fabs(dpos) > 1e-30) {
+        r = (float)(1.0 / dpos);
+        c = (float)(-pos_ref / dpos);
+    } else {
+        // A ray parallel to the planes never crosses them: a huge finite slope
+        // keeps the plane parameters finite and far outside any interval.
+        r = 1e30f;
+        c = (float)(-pos_ref * 1e30);
+    }
 }
 
 static void build_tables(cbct_geom *g) {
@@ -30,6 +39,7 @@ static void build_tables(cbct_geom *g) {
     const double a_ref = d.dso / d.dsd;
     const double xlo = -d.nx * d.vx / 2.0, ylo = -d.ny * d.vy / 2.0, zlo = -d.nz * d.vz / 2.0;
     g->xy.resize((size_t)d.n_views * d.nu);
+    g->xy0.resize((size_t)d.n_views * d.nu);
     g->trig.resize((size_t)d.n_views);
     for (int v = 0; v < d.n_views; ++v) {
         const double th = g->angles[(size_t)v];
@@ -40,21 +50,20 @@ static void build_tables(cbct_geom *g) {
             const double u = (iu + 0.5) * d.du - d.nu * d.du / 2.0;
             const double Px = (d.dso - d.dsd) * c - u * s;
             const double Py = (d.dso - d.dsd) * s + u * c;
-            float4 e;
-            axis_coeffs(Sx, Px - Sx, xlo, d.vx, a_ref, e.x, e.y);
-            axis_coeffs(Sy, Py - Sy, ylo, d.vy, a_ref, e.z, e.w);
-            g->xy[(size_t)v * d.nu + iu] = e;
+            float xi0, rx, cx, dx, eta0, ry, cy, dy;
+            axis_coeffs(Sx, Px - Sx, xlo, d.vx, a_ref, xi0, rx, cx, dx);
+            axis_coeffs(Sy, Py - Sy, ylo, d.vy, a_ref, eta0, ry, cy, dy);
+            g->xy[(size_t)v * d.nu + iu] = make_float4(rx, cx, ry, cy);
+            g->xy0[(size_t)v * d.nu + iu] = make_float2(xi0, eta0);
         }
     }
     g->zr.resize((size_t)d.nv);
     g->Lv2.resize((size_t)d.nv);
     for (int iv = 0; iv < d.nv; ++iv) {
         const double vmm = (iv + 0.5) * d.dv - d.nv * d.dv / 2.0;
-        float z0, rg;
-        axis_coeffs(0.0, vmm, zlo, d.vz, a_ref, z0, rg);
-        const double dz = vmm / d.vz;
-        const float s = rg > 0.0f ? 1.0f : -1.0f;
-        g->zr[(size_t)iv] = make_float4(z0, rg, (float)dz, s);
+        float z0, rg, cz, dz;
+        axis_coeffs(0.0, vmm, zlo, d.vz, a_ref, z0, rg, cz, dz);
+        g->zr[(size_t)iv] = make_float4(z0, rg, cz, dz);
         g->Lv2[(size_t)iv] = (float)(vmm * vmm);
     }
     g->Lu2.resize((size_t)d.nu);
@@ -100,8 +109,8 @@ static GeoK make_geok(const cbct_geom *g, const DevTables &t) {
     G.Z = d.nz + 2;
     G.hx = (float)d.vx; G.hy = (float)d.vy; G.hz = (float)d.vz;
     G.dso = (float)d.dso; G.dsd = (float)d.dsd; G.du = (float)d.du; G.dv = (float)d.dv;
-    G.xy = t.xy; G.zr = t.zr; G.Lu2 = t.Lu2; G.Lv2 = t.Lv2; G.trig = t.trig;
-    G.seghdr = t.seghdr; G.seg = t.seg; G.seg_stride = d.nx + d.ny + 2;
+    G.xy = t.xy; G.xy0 = t.xy0; G.zr = t.zr; G.Lu2 = t.Lu2; G.Lv2 = t.Lv2; G.trig = t.trig;
+    G.seghdr = t.seghdr; G.seg = t.seg; G.seg_stride = d.nx + d.ny - 1 + kSegPad;
     return G;
 }
 
@@ -116,11 +125,14 @@ GeoK geo_for_device(cbct_geom *g) {
             const cbct_geom_desc &d = g->d;
             try {
                 CBCT_HIP(hipMalloc(&t.xy, sizeof(float4) * g->xy.size()));
+                CBCT_HIP(hipMalloc(&t.xy0, sizeof(float2) * g->xy0.size()));
                 CBCT_HIP(hipMalloc(&t.zr, sizeof(float4) * g->zr.size()));
                 CBCT_HIP(hipMalloc(&t.Lu2, sizeof(float) * g->Lu2.size()));
                 CBCT_HIP(hipMalloc(&t.Lv2, sizeof(float) * g->Lv2.size()));
                 CBCT_HIP(hipMalloc(&t.trig, sizeof(float2) * g->trig.size()));
                 CBCT_HIP(hipMemcpy(t.xy, g->xy.data(), sizeof(float4) * g->xy.size(),
+                                   hipMemcpyHostToDevice));
+                CBCT_HIP(hipMemcpy(t.xy0, g->xy0.data(), sizeof(float2) * g->xy0.size(),
                                    hipMemcpyHostToDevice));
                 CBCT_HIP(hipMemcpy(t.zr, g->zr.data(), sizeof(float4) * g->zr.size(),
                                    hipMemcpyHostToDevice));
@@ -131,13 +143,13 @@ GeoK geo_for_device(cbct_geom *g) {
                 CBCT_HIP(hipMemcpy(t.trig, g->trig.data(), sizeof(float2) * g->trig.size(),
                                    hipMemcpyHostToDevice));
                 const size_t nr = (size_t)d.n_views * d.nu;
-                const size_t stride = (size_t)d.nx + d.ny + 2;
+                const size_t stride = (size_t)d.nx + d.ny - 1 + kSegPad;
                 CBCT_HIP(hipMalloc(&t.seghdr, sizeof(int2) * nr));
                 CBCT_HIP(hipMalloc(&t.seg, sizeof(int2) * nr * stride));
                 GeoK G = make_geok(g, t);
                 build_segment_tables(G, t.seghdr, t.seg);
             } catch (...) {
-                (void)hipFree(t.xy); (void)hipFree(t.zr); (void)hipFree(t.Lu2);
+                (void)hipFree(t.xy); (void)hipFree(t.xy0); (void)hipFree(t.zr); (void)hipFree(t.Lu2);
                 (void)hipFree(t.Lv2); (void)hipFree(t.trig); (void)hipFree(t.seghdr);
                 (void)hipFree(t.seg);
                 throw;
@@ -152,7 +164,7 @@ GeoK geo_for_device(cbct_geom *g) {
 
 size_t geom_table_bytes(const cbct_geom_desc &d) {
     const size_t nr = (size_t)d.n_views * d.nu;
-    return nr * (sizeof(float4) + sizeof(int2) * (1 + (size_t)d.nx + d.ny + 2)) +
+    return nr * (sizeof(float4) + sizeof(float2) + sizeof(int2) * ((size_t)d.nx + d.ny + kSegPad)) +
            (size_t)d.nv * (sizeof(float4) + sizeof(float)) + (size_t)d.nu * sizeof(float) +
            (size_t)d.n_views * sizeof(float2);
 }
@@ -199,6 +211,7 @@ void cbct_geom_destroy(cbct_geom *g) {
     for (auto &kv : g->dev) {
         (void)hipSetDevice(kv.first);
         (void)hipFree(kv.second.xy);
+        (void)hipFree(kv.second.xy0);
         (void)hipFree(kv.second.zr);
         (void)hipFree(kv.second.Lu2);
         (void)hipFree(kv.second.Lv2);

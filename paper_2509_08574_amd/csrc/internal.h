@@ -52,8 +52,9 @@ struct GeoK {
     int Z;               // nz + 2
     float hx, hy, hz;    // voxel size [mm] (detector footprints and row ranges only)
     float dso, dsd, du, dv;
-    const float4 *xy;    // [nviews*nu]: (xi0, rx, eta0, ry) -- see geom.cpp
-    const float4 *zr;    // [nv]: (z0, rg, dz, s)
+    const float4 *xy;    // [nviews*nu]: (rx, cx, ry, cy): x plane p at a' = fma(p, rx, cx)
+    const float2 *xy0;   // [nviews*nu]: (xi0, eta0): x, y index positions at a' = 0
+    const float4 *zr;    // [nv]: (z0, rg, cz, dz): z plane p at a' = fma(p, rg, cz)
     const float *Lu2;    // [nu]: dsd^2 + u^2
     const float *Lv2;    // [nv]: v^2
     const float2 *trig;  // [nviews]: (cos th, sin th)
@@ -61,15 +62,18 @@ struct GeoK {
     // device with the same float32 operations the kernels would use:
     // seghdr[r] = (a_in as float bits, number of segments n), and
     // seg[r*seg_stride + q] = (exit parameter ab as float bits, column j*nx + i)
-    // for q < n, followed by one dummy entry (column 0) so that a kernel may
-    // prefetch one entry past the end.
+    // for q < n, followed by kSegPad no-op entries (zero-length segment at the
+    // exit parameter, column 0) so that a kernel may read past the end.
     const int2 *seghdr;  // [nviews*nu]
     const int2 *seg;     // [nviews*nu*seg_stride]
-    int seg_stride;      // nx + ny + 2
+    int seg_stride;      // nx + ny - 1 + kSegPad (at most nx + ny - 1 segments)
 };
+
+constexpr int kSegPad = 4;
 
 struct DevTables {
     float4 *xy = nullptr;
+    float2 *xy0 = nullptr;
     float4 *zr = nullptr;
     float *Lu2 = nullptr;
     float *Lv2 = nullptr;
@@ -85,6 +89,7 @@ struct cbct_geom {
     std::vector<double> angles;
     // Host copies of the float32 tables (built once in cbct_geom_create).
     std::vector<float4> xy;
+    std::vector<float2> xy0;
     std::vector<float4> zr;
     std::vector<float> Lu2, Lv2;
     std::vector<float2> trig;

@@ -30,14 +30,14 @@ namespace cbct {
 // ---------------------------------------------------------------- segment tables
 
 // One thread per detector column (view, iu): the x-y traversal shared by all
-// rows of that column.  The sequence of (exit parameter, voxel column) is
-// exactly what k_fwd would compute on the fly, and the same values k_back
-// recomputes per column from the four bounding planes.
+// rows of that column.  The sequence of (exit parameter, voxel column) uses the
+// same plane values k_back recomputes per column from its four bounding planes.
 __global__ void __launch_bounds__(256)
 k_segtab(GeoK G, int2 *__restrict__ seghdr, int2 *__restrict__ seg) {
     const int r = blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= G.nviews * G.nu) return;
-    const float4 cxy = G.xy[r];
+    const float4 cxy = G.xy[r];    // (rx, cx, ry, cy)
+    const float2 c0 = G.xy0[r];    // (xi0, eta0)
     const float ax0 = plane_alpha(0.0f, cxy.x, cxy.y), axN = plane_alpha((float)G.nx, cxy.x, cxy.y);
     const float ay0 = plane_alpha(0.0f, cxy.z, cxy.w), ayN = plane_alpha((float)G.ny, cxy.z, cxy.w);
     const float a_in = fmaxf(fminf(ax0, axN), fminf(ay0, ayN));
@@ -45,12 +45,12 @@ k_segtab(GeoK G, int2 *__restrict__ seghdr, int2 *__restrict__ seg) {
     int2 *out = seg + (size_t)r * G.seg_stride;
     int n = 0;
     if (a_out > a_in) {
-        const int sx = cxy.y > 0.0f ? 1 : -1, sy = cxy.w > 0.0f ? 1 : -1;
-        int i = xy_cell(a_in, cxy.x, cxy.y, G.nx);
-        int j = xy_cell(a_in, cxy.z, cxy.w, G.ny);
+        const int sx = cxy.x > 0.0f ? 1 : -1, sy = cxy.z > 0.0f ? 1 : -1;
+        int i = xy_cell(a_in, c0.x, cxy.x, cxy.y, G.nx);
+        int j = xy_cell(a_in, c0.y, cxy.z, cxy.w, G.ny);
         float axn = plane_alpha((float)(i + (sx > 0)), cxy.x, cxy.y);
         float ayn = plane_alpha((float)(j + (sy > 0)), cxy.z, cxy.w);
-        const int nmax = G.seg_stride - 1;
+        const int nmax = G.seg_stride - kSegPad;
         while (n < nmax) {
             const float ab = fminf(axn, ayn);
             out[n++] = make_int2(__float_as_int(ab), j * G.nx + i);
@@ -66,7 +66,9 @@ k_segtab(GeoK G, int2 *__restrict__ seghdr, int2 *__restrict__ seg) {
             if ((unsigned)i >= (unsigned)G.nx || (unsigned)j >= (unsigned)G.ny) break;
         }
     }
-    out[n] = make_int2(__float_as_int(a_in), 0);  // dummy entry for one-ahead prefetch
+    // no-op entries: zero-length segments at the exit parameter, column 0
+    const int last = n > 0 ? out[n - 1].x : __float_as_int(a_in);
+    for (int q = 0; q < kSegPad; ++q) out[n + q] = make_int2(last, 0);
     seghdr[r] = make_int2(__float_as_int(a_in), n);
 }
 
@@ -84,11 +86,102 @@ void build_segment_tables(const GeoK &G, int2 *seghdr, int2 *seg) {
 
 // ---------------------------------------------------------------- forward
 
-// Column `col`'s cell (local index) `q` as an unsigned byte offset from the
-// uniform base `colm` (= column start - 1 cell), so the compiler can use the
-// scalar-base + 32-bit vector-offset load form.
-__device__ __forceinline__ float ld_cell(const float *colm, unsigned q) {
-    return *(const float *)((const char *)colm + (q << 2));
+// Detector rows are grouped in blocks of 64 that never straddle the detector's
+// centre: rows [0, h) (rays going down, v < 0) in blocks counted down from h,
+// rows [h, nv) (rays going up) in blocks counted up from h, h = nv / 2.  The z
+// direction is therefore uniform within a wave.
+__device__ __forceinline__ int row_blocks_lo(int nv) { return (nv / 2 + 63) >> 6; }
+__host__ __device__ inline int row_blocks(int nv) {
+    return ((nv / 2 + 63) >> 6) + ((nv - nv / 2 + 63) >> 6);
+}
+
+constexpr int kBufWord3 = 0x00020000;  // raw buffer resource, 32-bit dwords (gfx9 family)
+
+__device__ __forceinline__ float ldb(__amdgpu_buffer_rsrc_t r, int off) {
+    return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+}
+
+// One x-y segment [aa, ab] of a row's walk: chords c0 (cell k) and c1 (cell
+// k + DIR), z-crossing update, then the next column's reads are issued before
+// this segment's products so their latency overlaps the arithmetic.
+template <int DIR, int MODE>
+struct FwdLane {
+    float aa, an, pe, rg, cz, acc;
+    int ob;           // byte offset of the lower cell read, from one cell below the column
+    int obmax, nrec, Z, nz;
+    const float *vol_m;
+    unsigned cnt;
+
+    __device__ __forceinline__ void step(int2 e, float lo, float hi, int2 enext, float &nlo,
+                                         float &nhi) {
+        const float ab = __int_as_float(e.x);
+        const float m = fminf(ab, an);
+        const float c0 = m - aa;
+        const float c1 = ab - m;
+        const float vcur = DIR > 0 ? lo : hi, vnext = DIR > 0 ? hi : lo;
+        if constexpr (MODE == FWD_COUNT) {
+            const int kc = ob / 4 - (DIR > 0 ? 2 : 1);
+            cnt += (c0 > 0.0f && kc >= 0 && kc < nz) ? 1u : 0u;
+            cnt += (c1 > 0.0f && kc + DIR >= 0 && kc + DIR < nz) ? 1u : 0u;
+        }
+        if (an < ab) {
+            pe += (float)DIR;
+            an = plane_alpha(pe, rg, cz);
+            ob = DIR > 0 ? min(ob + 4, obmax) : max(ob - 4, 0);
+        }
+        const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+            (void *)(vol_m + (size_t)enext.y * Z), 0, nrec, kBufWord3);
+        nlo = ldb(rs, ob);
+        nhi = ldb(rs, ob + 4);
+        if constexpr (MODE != FWD_COUNT) {
+            acc = fmaf(c0, vcur, acc);
+            acc = fmaf(c1, vnext, acc);
+        }
+        aa = ab;
+    }
+};
+
+// Walk the x-y segments of one detector column for one row block moving in z
+// direction DIR.  Two segments per loop trip with alternating registers, so
+// the one-ahead reads never need to be copied (and waited for) early.
+template <int DIR, int MODE>
+__device__ __forceinline__ float fwd_walk(const GeoK &G, const float *vol, const int2 *sp,
+                                          int nseg, float a_in, float4 czr, unsigned &cnt) {
+    FwdLane<DIR, MODE> L;
+    int k;
+    zlane_init(a_in, czr, G.nz, k, L.pe, L.an);
+    L.aa = a_in;
+    L.rg = czr.y;
+    L.cz = czr.z;
+    L.acc = 0.0f;
+    L.cnt = 0;
+    L.ob = (k + (DIR > 0 ? 2 : 1)) * 4;
+    L.obmax = (G.nz + 2) * 4;
+    L.nrec = (G.nz + 4) * 4;
+    L.Z = G.Z;
+    L.nz = G.nz;
+    L.vol_m = vol - 1;
+    // Entries past the last segment are no-op segments (zero length, exit
+    // parameter, column 0), so the walk can run in whole pairs and read table
+    // entries one pair ahead.
+    int2 e0 = sp[0], e1 = sp[1], e2 = sp[2];
+    float a0, a1, b0, b1;
+    {
+        const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+            (void *)(L.vol_m + (size_t)e0.y * G.Z), 0, L.nrec, kBufWord3);
+        a0 = ldb(rs, L.ob);
+        a1 = ldb(rs, L.ob + 4);
+    }
+    for (int n = 0; n < nseg; n += 2) {
+        const int2 e3 = sp[n + 3], e4 = sp[n + 4];
+        L.step(e0, a0, a1, e1, b0, b1);
+        L.step(e1, b0, b1, e2, a0, a1);
+        e0 = e2;
+        e1 = e3;
+        e2 = e4;
+    }
+    cnt = L.cnt;
+    return L.acc;
 }
 
 template <int MODE>
@@ -99,17 +192,21 @@ k_fwd(GeoK G, FwdArgs a) {
     }
     const int lane = threadIdx.x & 63;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int nub = (G.nu + 3) >> 2, nrb = (G.nv + 63) >> 6;
+    const int nub = (G.nu + 3) >> 2, nrb = row_blocks(G.nv), nlo = row_blocks_lo(G.nv);
     const unsigned b = xcd_remap(blockIdx.x, gridDim.x);
     const int ub = (int)(b % (unsigned)nub);
     const unsigned t = b / (unsigned)nub;
     const int rb = (int)(t % (unsigned)nrb);
     const int view = (int)(t / (unsigned)nrb);
-    const int iu = ub * 4 + w, iv = rb * 64 + lane;
+    const int h = G.nv / 2;
+    const bool up = rb >= nlo;
+    const int iv = up ? h + (rb - nlo) * 64 + lane : h - (rb + 1) * 64 + lane;
+    const bool rowok = up ? iv < G.nv : iv >= 0;
+    const int iu = ub * 4 + w;
     const int iuc = iu < G.nu ? iu : G.nu - 1;
-    const int ivc = iv < G.nv ? iv : G.nv - 1;
+    const int ivc = rowok ? iv : (up ? G.nv - 1 : 0);
 
-    const int r = view * G.nu + iuc;              // wave-uniform
+    const int r = view * G.nu + iuc;  // wave-uniform
     const int2 hdr = G.seghdr[r];
     const int nseg = hdr.y;
     const int2 *sp = G.seg + (size_t)r * G.seg_stride;
@@ -118,47 +215,12 @@ k_fwd(GeoK G, FwdArgs a) {
     float acc = 0.0f;
     unsigned cnt = 0;
     if (nseg > 0) {
-        float aa = __int_as_float(hdr.x);
-        int k;
-        float pe, an;
-        zlane_init(aa, cz, G.nz, k, pe, an);
-        const float s = cz.w;
-        const int si = s > 0.0f ? 1 : -1;
-        unsigned q = (unsigned)(k + 2);   // local cell index + 1 (>= 1)
-        const unsigned qmax = (unsigned)G.nz + 2;
-        const float *vol_m = a.vol - 1;
-        int2 sg = sp[0];
-        const float *colm = vol_m + (size_t)sg.y * G.Z;
-        float v0 = ld_cell(colm, q), v1 = ld_cell(colm, q + si);
-        for (int n = 0; n < nseg; ++n) {
-            const float ab = __int_as_float(sg.x);
-            const float m = fminf(ab, an);
-            const float c0 = m - aa;
-            const float c1 = ab - m;
-            const unsigned qc = q;  // cells of this segment: qc and qc + si
-            if (an < ab) {
-                pe += s;
-                an = plane_alpha(pe, cz.x, cz.y);
-                q = min(max(q + si, 1u), qmax);
-            }
-            // next segment's column and cells (one-ahead loads; entry nseg is a dummy)
-            sg = sp[n + 1];
-            colm = vol_m + (size_t)sg.y * G.Z;
-            const float v0n = ld_cell(colm, q), v1n = ld_cell(colm, q + si);
-            if constexpr (MODE == FWD_COUNT) {
-                cnt += (c0 > 0.0f && qc >= 2 && qc <= (unsigned)G.nz + 1) ? 1u : 0u;
-                cnt += (c1 > 0.0f && qc + si >= 2 && qc + si <= (unsigned)G.nz + 1) ? 1u : 0u;
-            } else {
-                acc = fmaf(c0, v0, acc);
-                acc = fmaf(c1, v1, acc);
-            }
-            v0 = v0n;
-            v1 = v1n;
-            aa = ab;
-        }
+        const float a_in = __int_as_float(hdr.x);
+        acc = up ? fwd_walk<1, MODE>(G, a.vol, sp, nseg, a_in, cz, cnt)
+                 : fwd_walk<-1, MODE>(G, a.vol, sp, nseg, a_in, cz, cnt);
     }
 
-    const bool ok = iu < G.nu && iv < G.nv;
+    const bool ok = iu < G.nu && rowok;
     if constexpr (MODE == FWD_COUNT) {
         if (ok && cnt) atomicAdd(a.count, (unsigned long long)cnt);
         return;
@@ -187,7 +249,7 @@ k_fwd(GeoK G, FwdArgs a) {
 }
 
 int64_t forward_blocks(const GeoK &G) {
-    return (int64_t)G.nviews * ((G.nv + 63) / 64) * ((G.nu + 3) / 4);
+    return (int64_t)G.nviews * row_blocks(G.nv) * ((G.nu + 3) / 4);
 }
 
 void launch_forward(const GeoK &G, int mode, const FwdArgs &a, hipStream_t s) {
@@ -206,28 +268,29 @@ void launch_forward(const GeoK &G, int mode, const FwdArgs &a, hipStream_t s) {
 // ---------------------------------------------------------------- back
 
 // Gather form of A^T.  One wave owns one voxel column (i, j) and a block of up to
-// 64*NQ cells; lane l accumulates cells k = k0 + l + 64 q.  For every view, the
-// detector columns u whose rays cross (i, j) give the column interval [aa, ab]
-// (same float32 operations as the forward traversal); the rows that can meet
-// cell k are those whose height z = (a_ref + a') v lies in the cell for some a'
-// in [aa, ab], a range that follows from two divisions.  Each candidate row's
-// chord is the overlap of [aa, ab] with the cell's own z-plane interval,
+// 64*nq cells (nq <= 8); lane l accumulates cells k = k0 + l + 64 q.  For every
+// view, the detector columns u whose rays cross (i, j) give the column interval
+// [aa, ab] (same float32 plane values as the forward traversal); the rows that
+// can meet cell k are those whose height z = (a_ref + a') v lies in the cell for
+// some a' in [aa, ab], a range of at most C rows (C computed on the host from the
+// geometry).  Each candidate row's chord is the overlap of [aa, ab] with the
+// cell's own z-plane interval,
 //     c = max(0, min(ab, max(zA, zB)) - max(aa, min(zA, zB))),
-// zA, zB = (k - z0) rg, (k + 1 - z0) rg.  Because the forward kernel's cell
+// zA, zB = fma(k, rg, cz), fma(k + 1, rg, cz).  Because the forward kernel's cell
 // state satisfies entry(k) < aa <= exit(k) at every segment start and meets at
-// most one z plane per segment, this equals its c0 / c1 bit for bit, and is 0
-// for every cell the forward does not touch: the two kernels apply the same
-// matrix.  No atomics; every cell is summed in a fixed order.
-template <int NQ>
+// most one z plane per segment, this equals its c0 / c1 bit for bit and is 0 for
+// every cell the forward does not touch: the two kernels apply the same matrix.
+// No atomics; every cell is summed in a fixed order.
+template <int C>
 __global__ void __launch_bounds__(256)
 k_back(GeoK G, const float *__restrict__ yhat, float *__restrict__ out, const int *brk,
-       float a_ref, float z_lo_mm, float hz, int kspan) {
+       float a_ref, float z_lo_mm, int kspan, int nq) {
     if (brk && *brk == 2) return;
     extern __shared__ float lds[];
-    float2 *zrs = (float2 *)lds;  // per-row (z0, rg)
+    float2 *zrs = (float2 *)lds;  // per-row (rg, cz)
     for (int t = threadIdx.x; t < G.nv; t += 256) {
         const float4 z = G.zr[t];
-        zrs[t] = make_float2(z.x, z.y);
+        zrs[t] = make_float2(z.y, z.z);
     }
     __syncthreads();
 
@@ -241,13 +304,17 @@ k_back(GeoK G, const float *__restrict__ yhat, float *__restrict__ out, const in
     const int i = (int)(col % G.nx), j = (int)(col / G.nx);
     const int kbase = zs * kspan;
 
-    float acc[NQ], fk[NQ], zk0[NQ], zk1[NQ];
+    constexpr int QM = 8;
+    float acc[QM], fk[QM], zk0[QM], zk1[QM];
+    bool kok[QM];
 #pragma unroll
-    for (int q = 0; q < NQ; ++q) {
+    for (int q = 0; q < QM; ++q) {
         acc[q] = 0.0f;
-        fk[q] = (float)(kbase + lane + 64 * q);
-        zk0[q] = fmaf(fk[q], hz, z_lo_mm);   // cell's lower and upper z [mm]
-        zk1[q] = zk0[q] + hz;
+        const int k = kbase + lane + 64 * q;
+        kok[q] = q < nq && k < G.nz;
+        fk[q] = (float)k;
+        zk0[q] = fmaf(fk[q], G.hz, z_lo_mm);   // cell's lower and upper z [mm]
+        zk1[q] = zk0[q] + G.hz;
     }
     const float fi = (float)i, fj = (float)j;
     const float xlo = (fi - 0.5f * G.nx) * G.hx, xhi = xlo + G.hx;
@@ -287,22 +354,25 @@ k_back(GeoK G, const float *__restrict__ yhat, float *__restrict__ out, const in
             const float iA2 = __builtin_amdgcn_rcpf(a_ref + ab) * idv;
             const float *yrow = yhat + ((size_t)view * G.nu + iu) * G.nv;
 #pragma unroll
-            for (int q = 0; q < NQ; ++q) {
+            for (int q = 0; q < QM; ++q) {
+                if (q >= nq) break;
                 // rows whose centre v satisfies z_k <= A v <= z_k+1 for some A
                 const float flo = fmaf(zk0[q], zk0[q] >= 0.0f ? iA2 : iA1, fv_off);
                 const float fhi = fmaf(zk1[q], zk1[q] >= 0.0f ? iA1 : iA2, fv_off);
                 const float rlo = fmaxf(ceilf(flo - 1e-3f), 0.0f);
-                const float rhi = fminf(floorf(fhi + 1e-3f), rmax);
-                int r = (int)rlo;
-                const int r1 = fk[q] < (float)G.nz ? (int)rhi : -1;
+                const float rhi = kok[q] ? fminf(floorf(fhi + 1e-3f), rmax) : -1.0f;
+                const int r0 = (int)fminf(rlo, rmax);
                 float a = acc[q];
-                for (; r <= r1; ++r) {
+#pragma unroll
+                for (int c = 0; c < C; ++c) {
+                    const int r = min(r0 + c, G.nv - 1);
                     const float2 z = zrs[r];
-                    const float zA = (fk[q] - z.x) * z.y;
-                    const float zB = (fk[q] + 1.0f - z.x) * z.y;
+                    const float zA = plane_alpha(fk[q], z.x, z.y);
+                    const float zB = plane_alpha(fk[q] + 1.0f, z.x, z.y);
                     const float lo = fmaxf(aa, fminf(zA, zB));
                     const float hi = fminf(ab, fmaxf(zA, zB));
-                    a = fmaf(fmaxf(hi - lo, 0.0f), yrow[r], a);
+                    const float ch = (rlo + (float)c <= rhi) ? fmaxf(hi - lo, 0.0f) : 0.0f;
+                    a = fmaf(ch, yrow[r], a);
                 }
                 acc[q] = a;
             }
@@ -310,16 +380,29 @@ k_back(GeoK G, const float *__restrict__ yhat, float *__restrict__ out, const in
     }
     float *oc = out + (size_t)col * G.Z;
 #pragma unroll
-    for (int q = 0; q < NQ; ++q) {
-        const int k = kbase + lane + 64 * q;
-        if (k < G.nz && k < kbase + kspan) oc[k + 1] = acc[q];
-    }
+    for (int q = 0; q < QM; ++q)
+        if (kok[q]) oc[kbase + lane + 64 * q + 1] = acc[q];
     if (zs == 0 && lane == 0) oc[0] = 0.0f;
     if (zs == nzs - 1 && lane == 0) oc[G.nz + 1] = 0.0f;
 }
 
+// Upper bound on the number of detector rows that can meet one cell within one
+// column interval: rows span (z_k / A1 .. z_k+1 / A2) with A the absolute ray
+// parameter, so the span is at most (hz / A_min + R_z (A_max - A_min) / A_min^2) / dv.
+static int back_candidates(const GeoK &G) {
+    const double hx = G.nx * (double)G.hx / 2, hy = G.ny * (double)G.hy / 2;
+    const double rxy = std::sqrt(hx * hx + hy * hy);
+    const double umax = G.nu * (double)G.du / 2;
+    const double amin = (G.dso - rxy) / std::sqrt((double)G.dsd * G.dsd + umax * umax);
+    const double diag = std::sqrt((double)G.hx * G.hx + (double)G.hy * G.hy);
+    const double dA = diag / G.dsd;  // parameter extent of one column interval
+    const double rz = G.nz * (double)G.hz / 2;
+    const double span = (G.hz / amin + rz * dA / (amin * amin)) / G.dv;
+    return (int)std::floor(span * 1.02 + 0.01) + 1;
+}
+
 void launch_back(const GeoK &G, const float *yhat, float *out, const int *brk, hipStream_t s) {
-    // cells per wave: 64 * NQ, NQ <= 8; columns taller than 512 cells are split
+    // cells per wave: 64 * nq, nq <= 8; columns taller than 512 cells are split
     const int nq = std::min(8, (G.nz + 63) / 64);
     const int kspan = 64 * nq;
     const int nzs = (G.nz + kspan - 1) / kspan;
@@ -329,20 +412,18 @@ void launch_back(const GeoK &G, const float *yhat, float *out, const int *brk, h
     const size_t shm = sizeof(float2) * (size_t)G.nv;
     const float a_ref = G.dso / G.dsd;
     const float z_lo_mm = -0.5f * G.nz * G.hz;
+    const int C = back_candidates(G);
     auto go = [&](auto kern) {
         hipLaunchKernelGGL(kern, dim3((unsigned)nb), dim3(256), shm, s, G, yhat, out, brk, a_ref,
-                           z_lo_mm, G.hz, kspan);
+                           z_lo_mm, kspan, nq);
     };
-    switch (nq) {
-        case 1: go(k_back<1>); break;
-        case 2: go(k_back<2>); break;
-        case 3: go(k_back<3>); break;
-        case 4: go(k_back<4>); break;
-        case 5: go(k_back<5>); break;
-        case 6: go(k_back<6>); break;
-        case 7: go(k_back<7>); break;
-        default: go(k_back<8>); break;
-    }
+    if (C <= 2) go(k_back<2>);
+    else if (C <= 3) go(k_back<3>);
+    else if (C <= 4) go(k_back<4>);
+    else if (C <= 6) go(k_back<6>);
+    else if (C <= 8) go(k_back<8>);
+    else throw Error(CBCT_ERR_INVALID, "detector rows too fine for the back projector (more than "
+                                       "8 rows per voxel)");
     CBCT_HIP(hipGetLastError());
 }
 
