@@ -305,7 +305,7 @@ k_back(GeoK G, const float *__restrict__ yhat, float *__restrict__ out, const in
     const int kbase = zs * kspan;
 
     constexpr int QM = 8;
-    float acc[QM], fk[QM], zk0[QM], zk1[QM];
+    float acc[QM], fk[QM], fk1[QM], zk0[QM];
     bool kok[QM];
 #pragma unroll
     for (int q = 0; q < QM; ++q) {
@@ -313,15 +313,15 @@ k_back(GeoK G, const float *__restrict__ yhat, float *__restrict__ out, const in
         const int k = kbase + lane + 64 * q;
         kok[q] = q < nq && k < G.nz;
         fk[q] = (float)k;
-        zk0[q] = fmaf(fk[q], G.hz, z_lo_mm);   // cell's lower and upper z [mm]
-        zk1[q] = zk0[q] + G.hz;
+        fk1[q] = fk[q] + 1.0f;
+        zk0[q] = fmaf(fk[q], G.hz, z_lo_mm);   // cell's lower z [mm]
     }
     const float fi = (float)i, fj = (float)j;
     const float xlo = (fi - 0.5f * G.nx) * G.hx, xhi = xlo + G.hx;
     const float ylo = (fj - 0.5f * G.ny) * G.hy, yhi = ylo + G.hy;
     const float fu_scale = G.dsd / G.du, fu_off = 0.5f * G.nu - 0.5f;
     const float idv = 1.0f / G.dv, fv_off = 0.5f * G.nv - 0.5f;
-    const float rmax = (float)(G.nv - 1);
+    const float rwin = (float)(G.nv - C);  // last allowed window start
 
     for (int view = 0; view < G.nviews; ++view) {
         const float2 cs = G.trig[view];
@@ -356,25 +356,24 @@ k_back(GeoK G, const float *__restrict__ yhat, float *__restrict__ out, const in
 #pragma unroll
             for (int q = 0; q < QM; ++q) {
                 if (q >= nq) break;
-                // rows whose centre v satisfies z_k <= A v <= z_k+1 for some A
+                // the first row whose centre can satisfy z_k <= A v, then a window of C
+                // rows kept inside [0, nv): every row meeting the cell is in it, and
+                // rows that miss the cell contribute exactly zero below
                 const float flo = fmaf(zk0[q], zk0[q] >= 0.0f ? iA2 : iA1, fv_off);
-                const float fhi = fmaf(zk1[q], zk1[q] >= 0.0f ? iA1 : iA2, fv_off);
-                const float rlo = fmaxf(ceilf(flo - 1e-3f), 0.0f);
-                const float rhi = kok[q] ? fminf(floorf(fhi + 1e-3f), rmax) : -1.0f;
-                const int r0 = (int)fminf(rlo, rmax);
+                const int r0 = (int)fminf(fmaxf(ceilf(flo - 1e-3f), 0.0f), rwin);
+                const float2 *zq = zrs + r0;
+                const float *yq = yrow + r0;
                 float a = acc[q];
 #pragma unroll
                 for (int c = 0; c < C; ++c) {
-                    const int r = min(r0 + c, G.nv - 1);
-                    const float2 z = zrs[r];
+                    const float2 z = zq[c];
                     const float zA = plane_alpha(fk[q], z.x, z.y);
-                    const float zB = plane_alpha(fk[q] + 1.0f, z.x, z.y);
+                    const float zB = plane_alpha(fk1[q], z.x, z.y);
                     const float lo = fmaxf(aa, fminf(zA, zB));
                     const float hi = fminf(ab, fmaxf(zA, zB));
-                    const float ch = (rlo + (float)c <= rhi) ? fmaxf(hi - lo, 0.0f) : 0.0f;
-                    a = fmaf(ch, yrow[r], a);
+                    a = fmaf(fmaxf(hi - lo, 0.0f), yq[c], a);
                 }
-                acc[q] = a;
+                acc[q] = kok[q] ? a : 0.0f;
             }
         }
     }
@@ -412,18 +411,25 @@ void launch_back(const GeoK &G, const float *yhat, float *out, const int *brk, h
     const size_t shm = sizeof(float2) * (size_t)G.nv;
     const float a_ref = G.dso / G.dsd;
     const float z_lo_mm = -0.5f * G.nz * G.hz;
-    const int C = back_candidates(G);
+    // window of C rows; never more rows than the detector has
+    const int C = std::min(back_candidates(G), G.nv);
     auto go = [&](auto kern) {
         hipLaunchKernelGGL(kern, dim3((unsigned)nb), dim3(256), shm, s, G, yhat, out, brk, a_ref,
                            z_lo_mm, kspan, nq);
     };
-    if (C <= 2) go(k_back<2>);
-    else if (C <= 3) go(k_back<3>);
-    else if (C <= 4) go(k_back<4>);
-    else if (C <= 6) go(k_back<6>);
-    else if (C <= 8) go(k_back<8>);
-    else throw Error(CBCT_ERR_INVALID, "detector rows too fine for the back projector (more than "
-                                       "8 rows per voxel)");
+    switch (C) {
+        case 1: go(k_back<1>); break;
+        case 2: go(k_back<2>); break;
+        case 3: go(k_back<3>); break;
+        case 4: go(k_back<4>); break;
+        case 5: go(k_back<5>); break;
+        case 6: go(k_back<6>); break;
+        case 7: go(k_back<7>); break;
+        case 8: go(k_back<8>); break;
+        default:
+            throw Error(CBCT_ERR_INVALID, "detector rows too fine for the back projector (more "
+                                          "than 8 rows can meet one voxel)");
+    }
     CBCT_HIP(hipGetLastError());
 }
 
