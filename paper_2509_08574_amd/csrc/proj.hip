@@ -325,9 +325,9 @@ k_back(GeoK G, const float *__restrict__ yhat, float *__restrict__ out, const in
 
     for (int view = 0; view < G.nviews; ++view) {
         const float2 cs = G.trig[view];
-        // detector u range of the column's x-y square (conservative: every ray
-        // meeting the square lands between the extreme corner images; the
-        // one-pixel margin covers the approximate reciprocal)
+        // detector u range of the column's x-y square: a ray with a positive chord
+        // crosses the square's interior, so its pixel lies strictly between the
+        // extreme corner images (the small margin covers the approximate reciprocal)
         float umin = 3.0e38f, umax = -3.0e38f;
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
@@ -338,8 +338,8 @@ k_back(GeoK G, const float *__restrict__ yhat, float *__restrict__ out, const in
             umin = fminf(umin, fu);
             umax = fmaxf(umax, fu);
         }
-        const int iu0 = max(0, (int)floorf(umin) - 1);
-        const int iu1 = min(G.nu - 1, (int)ceilf(umax) + 1);
+        const int iu0 = max(0, (int)ceilf(umin - 1e-3f));
+        const int iu1 = min(G.nu - 1, (int)floorf(umax + 1e-3f));
         for (int iu = iu0; iu <= iu1; ++iu) {
             const float4 cxy = G.xy[(size_t)view * G.nu + iu];
             const float ex0 = plane_alpha(fi, cxy.x, cxy.y);
@@ -369,8 +369,11 @@ k_back(GeoK G, const float *__restrict__ yhat, float *__restrict__ out, const in
                     const float2 z = zq[c];
                     const float zA = plane_alpha(fk[q], z.x, z.y);
                     const float zB = plane_alpha(fk1[q], z.x, z.y);
-                    const float lo = fmaxf(aa, fminf(zA, zB));
-                    const float hi = fminf(ab, fmaxf(zA, zB));
+                    // med3(t, zA, zB) clamps t into the cell's interval: where the two
+                    // intervals overlap these are max(aa, zmin) and min(ab, zmax), and
+                    // where they do not the difference is <= 0 either way
+                    const float lo = __builtin_amdgcn_fmed3f(aa, zA, zB);
+                    const float hi = __builtin_amdgcn_fmed3f(ab, zA, zB);
                     a = fmaf(fmaxf(hi - lo, 0.0f), yq[c], a);
                 }
                 acc[q] = kok[q] ? a : 0.0f;
