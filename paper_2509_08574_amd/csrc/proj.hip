@@ -86,14 +86,10 @@ void build_segment_tables(const GeoK &G, int2 *seghdr, int2 *seg) {
 
 // ---------------------------------------------------------------- forward
 
-// Detector rows are grouped in blocks of 64 that never straddle the detector's
+// Detector rows are grouped in blocks that never straddle the detector's
 // centre: rows [0, h) (rays going down, v < 0) in blocks counted down from h,
 // rows [h, nv) (rays going up) in blocks counted up from h, h = nv / 2.  The z
 // direction is therefore uniform within a wave.
-__device__ __forceinline__ int row_blocks_lo(int nv) { return (nv / 2 + 63) >> 6; }
-__host__ __device__ inline int row_blocks(int nv) {
-    return ((nv / 2 + 63) >> 6) + ((nv - nv / 2 + 63) >> 6);
-}
 
 constexpr int kBufWord3 = 0x00020000;  // raw buffer resource, 32-bit dwords (gfx9 family)
 
@@ -141,104 +137,141 @@ struct FwdLane {
     }
 };
 
-// Walk the x-y segments of one detector column for one row block moving in z
-// direction DIR.  Two segments per loop trip with alternating registers, so
-// the one-ahead reads never need to be copied (and waited for) early.
-template <int DIR, int MODE>
-__device__ __forceinline__ float fwd_walk(const GeoK &G, const float *vol, const int2 *sp,
-                                          int nseg, float a_in, float4 czr, unsigned &cnt) {
-    FwdLane<DIR, MODE> L;
-    int k;
-    zlane_init(a_in, czr, G.nz, k, L.pe, L.an);
-    L.aa = a_in;
-    L.rg = czr.y;
-    L.cz = czr.z;
-    L.acc = 0.0f;
-    L.cnt = 0;
-    L.ob = (k + (DIR > 0 ? 2 : 1)) * 4;
-    L.obmax = (G.nz + 2) * 4;
-    L.nrec = (G.nz + 4) * 4;
-    L.Z = G.Z;
-    L.nz = G.nz;
-    L.vol_m = vol - 1;
-    // Entries past the last segment are no-op segments (zero length, exit
-    // parameter, column 0), so the walk can run in whole pairs and read table
-    // entries one pair ahead.
+// Walk the x-y segments of one detector column for RPL rows per lane moving in
+// z direction DIR.  Two segments per loop trip with alternating registers, so
+// the one-ahead reads never need to be copied (and waited for) early; with two
+// rows per lane the two walks share the segment stream and double the reads in
+// flight.
+template <int DIR, int MODE, int RPL>
+__device__ __forceinline__ void fwd_walk(const GeoK &G, const float *vol, const int2 *sp,
+                                         int nseg, float a_in, const float4 *czr, float *acc,
+                                         unsigned *cnt) {
+    FwdLane<DIR, MODE> L[RPL];
+    float a0[RPL], a1[RPL], b0[RPL], b1[RPL];
     int2 e0 = sp[0], e1 = sp[1], e2 = sp[2];
-    float a0, a1, b0, b1;
-    {
-        const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
-            (void *)(L.vol_m + (size_t)e0.y * G.Z), 0, L.nrec, kBufWord3);
-        a0 = ldb(rs, L.ob);
-        a1 = ldb(rs, L.ob + 4);
+    const __amdgpu_buffer_rsrc_t rs0 = __builtin_amdgcn_make_buffer_rsrc(
+        (void *)(vol - 1 + (size_t)e0.y * G.Z), 0, (G.nz + 4) * 4, kBufWord3);
+#pragma unroll
+    for (int p = 0; p < RPL; ++p) {
+        int k;
+        zlane_init(a_in, czr[p], G.nz, k, L[p].pe, L[p].an);
+        L[p].aa = a_in;
+        L[p].rg = czr[p].y;
+        L[p].cz = czr[p].z;
+        L[p].acc = 0.0f;
+        L[p].cnt = 0;
+        L[p].ob = (k + (DIR > 0 ? 2 : 1)) * 4;
+        L[p].obmax = (G.nz + 2) * 4;
+        L[p].nrec = (G.nz + 4) * 4;
+        L[p].Z = G.Z;
+        L[p].nz = G.nz;
+        L[p].vol_m = vol - 1;
+        a0[p] = ldb(rs0, L[p].ob);
+        a1[p] = ldb(rs0, L[p].ob + 4);
     }
+    // Entries past the last segment are no-op segments (zero length, exit
+    // parameter, column 0), so the walk runs in whole pairs and reads table
+    // entries one pair ahead.
     for (int n = 0; n < nseg; n += 2) {
         const int2 e3 = sp[n + 3], e4 = sp[n + 4];
-        L.step(e0, a0, a1, e1, b0, b1);
-        L.step(e1, b0, b1, e2, a0, a1);
+#pragma unroll
+        for (int p = 0; p < RPL; ++p) L[p].step(e0, a0[p], a1[p], e1, b0[p], b1[p]);
+#pragma unroll
+        for (int p = 0; p < RPL; ++p) L[p].step(e1, b0[p], b1[p], e2, a0[p], a1[p]);
         e0 = e2;
         e1 = e3;
         e2 = e4;
     }
-    cnt = L.cnt;
-    return L.acc;
+#pragma unroll
+    for (int p = 0; p < RPL; ++p) {
+        acc[p] = L[p].acc;
+        cnt[p] = L[p].cnt;
+    }
 }
 
-template <int MODE>
+// Rows per lane of the forward kernel: two when each detector half has at
+// least 128 rows.
+__host__ __device__ inline int fwd_rpl(int nv) { return nv / 2 >= 128 ? 2 : 1; }
+
+template <int MODE, int RPL>
 __global__ void __launch_bounds__(256)
 k_fwd(GeoK G, FwdArgs a) {
     if constexpr (MODE == FWD_SOLVER) {
         if (*a.brk == 2) return;
     }
+    constexpr int RB = 64 * RPL;  // rows per wave
     const int lane = threadIdx.x & 63;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int nub = (G.nu + 3) >> 2, nrb = row_blocks(G.nv), nlo = row_blocks_lo(G.nv);
+    const int h = G.nv / 2;
+    const int nlo = (h + RB - 1) / RB, nhi = (G.nv - h + RB - 1) / RB, nrb = nlo + nhi;
+    const int nub = (G.nu + 3) >> 2;
     const unsigned b = xcd_remap(blockIdx.x, gridDim.x);
     const int ub = (int)(b % (unsigned)nub);
     const unsigned t = b / (unsigned)nub;
     const int rb = (int)(t % (unsigned)nrb);
     const int view = (int)(t / (unsigned)nrb);
-    const int h = G.nv / 2;
     const bool up = rb >= nlo;
-    const int iv = up ? h + (rb - nlo) * 64 + lane : h - (rb + 1) * 64 + lane;
-    const bool rowok = up ? iv < G.nv : iv >= 0;
     const int iu = ub * 4 + w;
     const int iuc = iu < G.nu ? iu : G.nu - 1;
-    const int ivc = rowok ? iv : (up ? G.nv - 1 : 0);
+
+    int iv[RPL], ivc[RPL];
+    bool rowok[RPL];
+    float4 czr[RPL];
+#pragma unroll
+    for (int p = 0; p < RPL; ++p) {
+        iv[p] = up ? h + (rb - nlo) * RB + 64 * p + lane : h - (rb + 1) * RB + 64 * p + lane;
+        rowok[p] = up ? iv[p] < G.nv : iv[p] >= 0;
+        ivc[p] = rowok[p] ? iv[p] : (up ? G.nv - 1 : 0);
+        czr[p] = G.zr[ivc[p]];
+    }
 
     const int r = view * G.nu + iuc;  // wave-uniform
     const int2 hdr = G.seghdr[r];
     const int nseg = hdr.y;
     const int2 *sp = G.seg + (size_t)r * G.seg_stride;
-    const float4 cz = G.zr[ivc];
 
-    float acc = 0.0f;
-    unsigned cnt = 0;
+    float acc[RPL];
+    unsigned cnt[RPL];
+#pragma unroll
+    for (int p = 0; p < RPL; ++p) {
+        acc[p] = 0.0f;
+        cnt[p] = 0;
+    }
     if (nseg > 0) {
         const float a_in = __int_as_float(hdr.x);
-        acc = up ? fwd_walk<1, MODE>(G, a.vol, sp, nseg, a_in, cz, cnt)
-                 : fwd_walk<-1, MODE>(G, a.vol, sp, nseg, a_in, cz, cnt);
+        if (up)
+            fwd_walk<1, MODE, RPL>(G, a.vol, sp, nseg, a_in, czr, acc, cnt);
+        else
+            fwd_walk<-1, MODE, RPL>(G, a.vol, sp, nseg, a_in, czr, acc, cnt);
     }
 
-    const bool ok = iu < G.nu && rowok;
     if constexpr (MODE == FWD_COUNT) {
-        if (ok && cnt) atomicAdd(a.count, (unsigned long long)cnt);
+        unsigned c = 0;
+#pragma unroll
+        for (int p = 0; p < RPL; ++p) c += (iu < G.nu && rowok[p]) ? cnt[p] : 0u;
+        if (c) atomicAdd(a.count, (unsigned long long)c);
         return;
     }
-    const size_t o = ((size_t)view * G.nu + iuc) * G.nv + ivc;
-    const float L2 = G.Lu2[iuc] + G.Lv2[ivc];
-    if constexpr (MODE == FWD_PLAIN) {
-        if (ok) a.out[o] = sqrtf(L2) * acc;
-    } else {
-        // u-hat = L * u with u = s1 * (A v) + s2 * u_old  =>  u-hat = s1 L^2 acc + s2 u-hat_old
-        const float s1 = (float)*a.s1, s2 = (float)*a.s2;
-        float un = s1 * (L2 * acc);
-        if (s2 != 0.0f) un = fmaf(s2, a.uin[o], un);
-        double sq = 0.0;
-        if (ok) {
-            a.out[o] = un;
-            sq = (double)un * (double)un / (double)L2;  // |u|^2 = u-hat^2 / L^2
+    double sq = 0.0;
+#pragma unroll
+    for (int p = 0; p < RPL; ++p) {
+        const bool ok = iu < G.nu && rowok[p];
+        const size_t o = ((size_t)view * G.nu + iuc) * G.nv + ivc[p];
+        const float L2 = G.Lu2[iuc] + G.Lv2[ivc[p]];
+        if constexpr (MODE == FWD_PLAIN) {
+            if (ok) a.out[o] = sqrtf(L2) * acc[p];
+        } else {
+            // u-hat = L * u, u = s1 * (A v) + s2 * u_old  =>  u-hat = s1 L^2 acc + s2 u-hat_old
+            const float s1 = (float)*a.s1, s2 = (float)*a.s2;
+            float un = s1 * (L2 * acc[p]);
+            if (s2 != 0.0f) un = fmaf(s2, a.uin[o], un);
+            if (ok) {
+                a.out[o] = un;
+                sq += (double)un * (double)un / (double)L2;  // |u|^2 = u-hat^2 / L^2
+            }
         }
+    }
+    if constexpr (MODE == FWD_SOLVER) {
         // block reduction (fixed order -> deterministic)
         for (int off = 32; off > 0; off >>= 1) sq += __shfl_xor(sq, off, 64);
         __shared__ double red[4];
@@ -249,19 +282,30 @@ k_fwd(GeoK G, FwdArgs a) {
 }
 
 int64_t forward_blocks(const GeoK &G) {
-    return (int64_t)G.nviews * row_blocks(G.nv) * ((G.nu + 3) / 4);
+    const int RB = 64 * fwd_rpl(G.nv), h = G.nv / 2;
+    const int nrb = (h + RB - 1) / RB + (G.nv - h + RB - 1) / RB;
+    return (int64_t)G.nviews * nrb * ((G.nu + 3) / 4);
+}
+
+template <int RPL>
+static void launch_forward_rpl(const GeoK &G, int mode, const FwdArgs &a, hipStream_t s,
+                               dim3 grid) {
+    const dim3 block(256);
+    if (mode == FWD_PLAIN)
+        hipLaunchKernelGGL((k_fwd<FWD_PLAIN, RPL>), grid, block, 0, s, G, a);
+    else if (mode == FWD_SOLVER)
+        hipLaunchKernelGGL((k_fwd<FWD_SOLVER, RPL>), grid, block, 0, s, G, a);
+    else
+        hipLaunchKernelGGL((k_fwd<FWD_COUNT, RPL>), grid, block, 0, s, G, a);
 }
 
 void launch_forward(const GeoK &G, int mode, const FwdArgs &a, hipStream_t s) {
     const int64_t nb = forward_blocks(G);
     if (nb > 0x7fffffff) throw Error(CBCT_ERR_INVALID, "forward grid too large");
-    dim3 grid((unsigned)nb), block(256);
-    if (mode == FWD_PLAIN)
-        hipLaunchKernelGGL(k_fwd<FWD_PLAIN>, grid, block, 0, s, G, a);
-    else if (mode == FWD_SOLVER)
-        hipLaunchKernelGGL(k_fwd<FWD_SOLVER>, grid, block, 0, s, G, a);
+    if (fwd_rpl(G.nv) == 2)
+        launch_forward_rpl<2>(G, mode, a, s, dim3((unsigned)nb));
     else
-        hipLaunchKernelGGL(k_fwd<FWD_COUNT>, grid, block, 0, s, G, a);
+        launch_forward_rpl<1>(G, mode, a, s, dim3((unsigned)nb));
     CBCT_HIP(hipGetLastError());
 }
 
