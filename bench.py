@@ -39,6 +39,7 @@ def main():
     ap.add_argument("--prior", default="720", choices=["720", "truth"],
                     help="prior image: 720-view plain-LSQR reconstruction, or the true base object")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--fp32-only", action="store_true", help="skip the mixed-precision forms")
     ap.add_argument("--op-reps", type=int, default=10)
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also run one plain device copy of this many MiB (profiler calibration)")
@@ -127,6 +128,31 @@ def main():
     log(f"[bench] {args.steps} steps: {ms_per_step:.1f} ms/recon; rel err vs truth "
         f"{err_truth:.4f} (prior {err_prior:.4f})")
 
+    # ---------------- precision forms: s/recon at this workload
+    forms = {}
+    if not args.fp32_only:
+        for name, pr in (("mixed_bf16", cbct.PREC_MIXED_BF16), ("mixed_f16", cbct.PREC_MIXED_F16)):
+            pm = cbct.SolveParams(sp["alpha"], sp["lam"], sp["tau"], sp["n_outer"],
+                                  sp["n_inner"], precision=pr)
+            wsm = cbct.alloc_workspace(g, pm, device=dev)
+            xm = torch.empty_like(xprior)
+            xm.copy_(xprior)
+            cbct.solve(g, b_d, xprior, xm, pm, workspace=wsm, report=False)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            for _ in range(args.steps):
+                xm.copy_(xprior)
+                cbct.solve(g, b_d, xprior, xm, pm, workspace=wsm, report=False)
+            torch.cuda.synchronize()
+            sec = (time.perf_counter() - t) / args.steps
+            forms[name] = {"s_per_recon": round(sec, 4),
+                           "speedup_vs_fp32": round(ms_per_step / 1e3 / sec, 3),
+                           "rel_l2_vs_fp32_gpu": float(torch.linalg.norm(xm - x)
+                                                       / torch.linalg.norm(x))}
+            del wsm
+            log(f"[bench] {name}: {sec * 1e3:.1f} ms/recon")
+    forms["fp32"] = {"s_per_recon": round(ms_per_step / 1e3, 4), "speedup_vs_fp32": 1.0}
+
     # ---------------- isolated projector kernels (HIP events on this stream)
     vf, voff, pf = cbct.col_sizes(g)
     xc = cbct.vol_to_cols(g, cur_d)
@@ -188,6 +214,33 @@ def main():
                "s_per_recon_extrapolated": round(products * (t_A + t_AT), 1)}
         log(f"[bench] oracle: A {t_A:.1f}s, A^T {t_AT:.1f}s per full application")
 
+        # every precision form against the FP64 oracle on the full 64^3 / 48-view
+        # solve (3 x 5 iterations), which the oracle finishes in seconds
+        gd1 = synth.geometry("c1")
+        sp1 = synth.SOLVE_PARAMS["c1"]
+        og1 = orc.Geometry.from_dict(gd1)
+        prior1, cur1 = synth.c1_case()
+        b1 = synth.noisy_line_integrals(orc.forward(og1, cur1), sp1["I0"], seed=101)
+        b1 = b1.astype(np.float32).astype(np.float64)
+        prior1 = prior1.astype(np.float32).astype(np.float64)
+        t = time.perf_counter()
+        ref1 = orc.irn_piccs(og1, b1, prior1, prior1, sp1["alpha"], sp1["lam"], sp1["tau"],
+                             sp1["n_outer"], sp1["n_inner"])
+        t_or1 = time.perf_counter() - t
+        g1 = cbct.Geometry.from_dict(gd1)
+        for name, pr in (("fp32", cbct.PREC_FP32), ("mixed_bf16", cbct.PREC_MIXED_BF16),
+                         ("mixed_f16", cbct.PREC_MIXED_F16)):
+            if name not in forms:
+                continue
+            x1 = torch.from_numpy(prior1.astype(np.float32)).to(dev)
+            cbct.solve(g1, torch.from_numpy(b1.astype(np.float32)).to(dev), x1.clone(), x1,
+                       cbct.SolveParams(sp1["alpha"], sp1["lam"], sp1["tau"], sp1["n_outer"],
+                                        sp1["n_inner"], precision=pr), report=False)
+            xg1 = x1.cpu().numpy().astype(np.float64)
+            forms[name]["rel_l2_vs_fp64_oracle_c1"] = float(
+                np.linalg.norm(xg1 - ref1.x) / np.linalg.norm(ref1.x))
+        cpu["oracle_c1_solve_s"] = round(t_or1, 2)
+
     out = {
         "metric": "Gvoxel-proj/s for A and A^T; s/recon + p99 latency, FP32 vs mixed",
         "value": round(value, 3),
@@ -217,6 +270,7 @@ def main():
             "rel_err_prior_vs_truth": round(err_prior, 5),
             "prior": args.prior,
         },
+        "precision_forms": forms,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

@@ -119,15 +119,18 @@ size_t geom_table_bytes(const cbct_geom_desc &d);
 enum FwdMode { FWD_PLAIN = 0, FWD_SOLVER = 1, FWD_COUNT = 2 };
 
 struct FwdArgs {
-    const float *vol;        // padded column volume base (cell (col, -1))
+    const void *vol;         // padded column volume base (cell (col, -1)); element type
+                             // float32, bf16 or fp16 as passed to launch_forward
     float *out;              // column projections
     const float *uin;        // FWD_SOLVER: previous u-hat (may alias out)
     const double *s1, *s2;   // FWD_SOLVER: device scalars
     double *partial;         // FWD_SOLVER: one double per block
     const int *brk;          // FWD_SOLVER: breakdown flag (2 = stopped)
     unsigned long long *count;  // FWD_COUNT
+    float scale;             // FWD_PLAIN: output multiplier (value of one stored unit)
 };
-void launch_forward(const GeoK &G, int mode, const FwdArgs &a, hipStream_t s);
+void launch_forward(const GeoK &G, int mode, const FwdArgs &a, hipStream_t s,
+                    int dtype = CBCT_F32);
 int64_t forward_blocks(const GeoK &G);
 
 // Back projection of column projections y-hat (already multiplied by the ray

@@ -12,6 +12,9 @@
 // Data-space vector: u_b (projections, stored as u-hat = L * u_b in column
 // layout, L = ray length), u1 and u2 (three difference components each, in
 // padded column volumes).  Model-space vectors: padded column volumes.
+#include <hip/hip_bf16.h>
+#include <hip/hip_fp16.h>
+
 #include <algorithm>
 #include <cmath>
 
@@ -26,6 +29,7 @@ enum Sc {
     SC_XW_A, SC_XW_B, SC_XW_C,
     SC_M1, SC_P1, SC_ZERO,
     SC_INNER_DONE, SC_OUTER_DONE, SC_NBRK,
+    SC_V16_SCALE,  // power-of-two scale of the 16-bit shadow of V (mixed forms)
     SC_COUNT = 32
 };
 // flag 0: breakdown state of the current inner solve: 0 running, 1 last
@@ -187,17 +191,34 @@ k_regA(GeoK G, const float *__restrict__ t, const float *__restrict__ W1,
 
 // x += a w;  w <- b V + c w   (LSQR's solution and direction updates).  Works
 // on the whole padded array: pads are zero in every operand and stay zero.
+// Mixed forms (DT = bf16 / fp16) also write the forward projector's 16-bit
+// shadow V16 = V * scale (scale a power of two, exact).
+template <int DT>
 __global__ void __launch_bounds__(256)
-k_xw(float *__restrict__ x, float *__restrict__ w, const float *__restrict__ V, int64_t n,
-     const double *sc, const int *brk) {
+k_xw(float *__restrict__ x, float *__restrict__ w, const float *__restrict__ V,
+     unsigned short *__restrict__ V16, int64_t n, const double *sc, const int *brk) {
     if (*brk == 2) return;
     const float a = (float)sc[SC_XW_A], b = (float)sc[SC_XW_B], c = (float)sc[SC_XW_C];
+    const float sv = (float)sc[SC_V16_SCALE];
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += stride) {
         const float wo = (a != 0.0f || c != 0.0f) ? w[t] : 0.0f;
         if (a != 0.0f) x[t] = fmaf(a, wo, x[t]);
-        w[t] = fmaf(c, wo, b * V[t]);
+        const float v = V[t];
+        w[t] = fmaf(c, wo, b * v);
+        if constexpr (DT == CBCT_BF16) {
+            V16[t] = __bfloat16_as_ushort(__float2bfloat16(v * sv));
+        } else if constexpr (DT == CBCT_F16) {
+            V16[t] = __half_as_ushort(__float2half(v * sv));
+        }
     }
+}
+
+// Power-of-two scale bringing the entries of a vector of norm nrm over m
+// entries to root-mean-square about 1 (fp16 range); 1 for bf16 / fp32.
+__device__ __forceinline__ double shadow_scale(int dt, double nrm, double m) {
+    if (dt != CBCT_F16 || !(nrm > 0.0)) return 1.0;
+    return exp2(rint(log2(sqrt(m) / nrm)));
 }
 
 // ---------------------------------------------------------------- reductions + recurrence
@@ -209,7 +230,7 @@ enum RedMode { RED_INIT_BETA = 0, RED_INIT_ALPHA, RED_BETA, RED_ALPHA };
 template <int MODE>
 __global__ void __launch_bounds__(1024)
 k_red(const double *__restrict__ p0, int64_t n0, const double *__restrict__ p1, int64_t n1,
-      double *sc, int *fl, double *hist, int it) {
+      double *sc, int *fl, double *hist, int it, int dt, double nvox) {
     const int brk = fl[0];
     if (brk == 2) return;
     if (MODE == RED_BETA && brk == 1) {
@@ -242,7 +263,10 @@ k_red(const double *__restrict__ p0, int64_t n0, const double *__restrict__ p1, 
         sc[SC_XW_A] = 0.0;
         sc[SC_XW_B] = 1.0 / nrm;
         sc[SC_XW_C] = 0.0;
-        sc[SC_FWD_S1] = sc[SC_REG_S1] = 1.0 / nrm;
+        const double sv = shadow_scale(dt, nrm, nvox);
+        sc[SC_V16_SCALE] = sv;
+        sc[SC_FWD_S1] = 1.0 / (nrm * sv);  // the projector reads V * sv
+        sc[SC_REG_S1] = 1.0 / nrm;
         sc[SC_FWD_S2] = sc[SC_REG_S2] = -nrm / beta;
     } else if (MODE == RED_BETA) {          // beta u = A~ v - alpha u
         const double alpha = sc[SC_ALPHA];
@@ -269,7 +293,10 @@ k_red(const double *__restrict__ p0, int64_t n0, const double *__restrict__ p1, 
             fl[0] = 1;  // apply this last update, then stop
             sc[SC_FWD_S1] = sc[SC_FWD_S2] = sc[SC_REG_S1] = sc[SC_REG_S2] = 0.0;
         } else {
-            sc[SC_FWD_S1] = sc[SC_REG_S1] = 1.0 / alpha;
+            const double sv = shadow_scale(dt, alpha, nvox);
+            sc[SC_V16_SCALE] = sv;
+            sc[SC_FWD_S1] = 1.0 / (alpha * sv);  // the projector reads V * sv
+            sc[SC_REG_S1] = 1.0 / alpha;
             sc[SC_FWD_S2] = sc[SC_REG_S2] = -alpha / beta;
         }
     }
@@ -280,6 +307,7 @@ __global__ void k_solve_begin(double *sc, int *fl, double *hist, int nh) {
     for (int q = 0; q < nh; ++q) hist[q] = __longlong_as_double(0x7ff8000000000000LL);  // NaN
     sc[SC_M1] = -1.0;
     sc[SC_P1] = 1.0;
+    sc[SC_V16_SCALE] = 1.0;
     fl[0] = 0;
 }
 
@@ -298,6 +326,9 @@ __global__ void k_solve_end(double *sc, int *fl) {
 
 struct Workspace {
     float *x, *xp, *w, *V, *t, *W1, *W2, *u1, *u2;  // padded column bases (P pointers)
+    unsigned short *V16;                            // 16-bit shadow base (P), mixed forms
+    unsigned short *V16buf;                         // its allocation start
+    size_t v16_bytes;
     int64_t cstride;                                // floats between components
     float *bhat, *uhat;
     double *pf, *pr, *pa;  // partials: forward, regF, regA
@@ -327,6 +358,11 @@ static Workspace carve(const cbct_geom *g, const GeoK &G, const piccs_params *p,
     W.x = P(0); W.xp = P(1); W.w = P(2); W.V = P(3); W.t = P(4); W.W1 = P(5); W.W2 = P(6);
     W.u1 = P(7); W.u2 = P(10);
     W.cstride = (int64_t)(vb / sizeof(float));
+    if (p->precision != CBCT_PREC_FP32) {
+        W.v16_bytes = al(sizeof(unsigned short) * (size_t)g->pad_floats());
+        W.V16buf = (unsigned short *)take(W.v16_bytes);
+        W.V16 = W.V16buf ? W.V16buf + kGuard : nullptr;
+    }
     W.bhat = (float *)take(pb);
     W.uhat = (float *)take(pb);
     W.pf = (double *)take(sizeof(double) * (size_t)W.nf);
@@ -346,8 +382,9 @@ static void check_params(const piccs_params *p) {
                  "alpha, lambda, tau must be finite and >= 0");
     CBCT_REQUIRE(p->n_outer >= 1 && p->n_inner >= 1 && p->n_outer <= 100000 &&
                      p->n_inner <= 100000, "n_outer and n_inner must be >= 1");
-    CBCT_REQUIRE(p->precision == CBCT_PREC_FP32,
-                 "only CBCT_PREC_FP32 is available in this build");
+    CBCT_REQUIRE(p->precision == CBCT_PREC_FP32 || p->precision == CBCT_PREC_MIXED_BF16 ||
+                     p->precision == CBCT_PREC_MIXED_F16,
+                 "unknown precision");
     CBCT_REQUIRE(p->reorth == 0, "reorthogonalisation is not available in this build");
 }
 
@@ -442,6 +479,22 @@ int piccs_krylov_solve(const cbct_geom *gc, const float *b, const float *xp, flo
 
         // padded column copies of the inputs (pads and guards zero)
         launch_fill(W.x - kGuard, W.cstride * 13, 0.0f, s);
+        const int dt = p->precision == CBCT_PREC_MIXED_BF16   ? CBCT_BF16
+                       : p->precision == CBCT_PREC_MIXED_F16 ? CBCT_F16
+                                                              : CBCT_F32;
+        if (dt != CBCT_F32) launch_fill((float *)W.V16buf, (int64_t)(W.v16_bytes / 4), 0.0f, s);
+        const double nvox = (double)g->n_vox();
+        auto xw = [&]() {
+            if (dt == CBCT_BF16)
+                hipLaunchKernelGGL(k_xw<CBCT_BF16>, dim3(4096), dim3(256), 0, s, W.x, W.w, W.V,
+                                   W.V16, ncz, W.sc, W.fl);
+            else if (dt == CBCT_F16)
+                hipLaunchKernelGGL(k_xw<CBCT_F16>, dim3(4096), dim3(256), 0, s, W.x, W.w, W.V,
+                                   W.V16, ncz, W.sc, W.fl);
+            else
+                hipLaunchKernelGGL(k_xw<CBCT_F32>, dim3(4096), dim3(256), 0, s, W.x, W.w, W.V,
+                                   (unsigned short *)nullptr, ncz, W.sc, W.fl);
+        };
         vol_to_cols(G, x, W.x, s);
         vol_to_cols(G, xp, W.xp, s);
         proj_to_cols(G, b, W.bhat, true, s);  // b-hat = L * b
@@ -465,33 +518,33 @@ int piccs_krylov_solve(const cbct_geom *gc, const float *b, const float *xp, flo
                                W.W2, W.u1, W.u2, W.cstride, alpha, lam, W.sc + SC_M1,
                                W.sc + SC_ZERO, W.pr, W.fl);
             hipLaunchKernelGGL(k_red<RED_INIT_BETA>, dim3(1), dim3(1024), 0, s, W.pf, W.nf,
-                               W.pr, W.nr, W.sc, W.fl, W.hist, 0);
+                               W.pr, W.nr, W.sc, W.fl, W.hist, 0, dt, nvox);
             // alpha_1 v_1 = A~^T u_1
             launch_back(G, W.uhat, W.t, W.fl, s);
             hipLaunchKernelGGL(k_regA, dim3(nvb), dim3(256), 0, s, G, W.t, W.W1, W.W2, W.u1,
                                W.u2, W.cstride, alpha, lam, W.V, W.sc + SC_BACK_S1,
                                W.sc + SC_BACK_S2, W.pa, W.fl);
             hipLaunchKernelGGL(k_red<RED_INIT_ALPHA>, dim3(1), dim3(1024), 0, s, W.pa, W.nr,
-                               (const double *)nullptr, (int64_t)0, W.sc, W.fl, W.hist, 0);
-            hipLaunchKernelGGL(k_xw, dim3(4096), dim3(256), 0, s, W.x, W.w, W.V, ncz,
-                               W.sc, W.fl);
+                               (const double *)nullptr, (int64_t)0, W.sc, W.fl, W.hist, 0, dt,
+                               nvox);
+            xw();
             for (int ki = 0; ki < p->n_inner; ++ki, ++it_global) {
-                fa.vol = W.V; fa.uin = W.uhat; fa.s1 = W.sc + SC_FWD_S1; fa.s2 = W.sc + SC_FWD_S2;
-                launch_forward(G, FWD_SOLVER, fa, s);
+                fa.vol = dt == CBCT_F32 ? (const void *)W.V : (const void *)W.V16;
+                fa.uin = W.uhat; fa.s1 = W.sc + SC_FWD_S1; fa.s2 = W.sc + SC_FWD_S2;
+                launch_forward(G, FWD_SOLVER, fa, s, dt);
                 hipLaunchKernelGGL(k_regF<false>, dim3(nvb), dim3(256), 0, s, G, W.V,
                                    (const float *)nullptr, W.W1, W.W2, W.u1, W.u2, W.cstride,
                                    alpha, lam, W.sc + SC_REG_S1, W.sc + SC_REG_S2, W.pr, W.fl);
                 hipLaunchKernelGGL(k_red<RED_BETA>, dim3(1), dim3(1024), 0, s, W.pf, W.nf,
-                                   W.pr, W.nr, W.sc, W.fl, W.hist, it_global);
+                                   W.pr, W.nr, W.sc, W.fl, W.hist, it_global, dt, nvox);
                 launch_back(G, W.uhat, W.t, W.fl, s);
                 hipLaunchKernelGGL(k_regA, dim3(nvb), dim3(256), 0, s, G, W.t, W.W1, W.W2, W.u1,
                                    W.u2, W.cstride, alpha, lam, W.V, W.sc + SC_BACK_S1,
                                    W.sc + SC_BACK_S2, W.pa, W.fl);
                 hipLaunchKernelGGL(k_red<RED_ALPHA>, dim3(1), dim3(1024), 0, s, W.pa, W.nr,
                                    (const double *)nullptr, (int64_t)0, W.sc, W.fl, W.hist,
-                                   it_global);
-                hipLaunchKernelGGL(k_xw, dim3(4096), dim3(256), 0, s, W.x, W.w, W.V, ncz,
-                                   W.sc, W.fl);
+                                   it_global, dt, nvox);
+                xw();
             }
         }
         hipLaunchKernelGGL(k_solve_end, dim3(1), dim3(1), 0, s, W.sc, W.fl);

@@ -97,15 +97,42 @@ __device__ __forceinline__ float ldb(__amdgpu_buffer_rsrc_t r, int off) {
     return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
 }
 
+// Storage element of the forward projector's input volume: float32, or a
+// 16-bit shadow (bf16, or fp16 holding value * scale) widened on load.
+template <int DT>
+struct Elem;
+template <>
+struct Elem<CBCT_F32> {
+    static constexpr int size = 4;
+    __device__ static float load(__amdgpu_buffer_rsrc_t r, int off) { return ldb(r, off); }
+};
+template <>
+struct Elem<CBCT_BF16> {
+    static constexpr int size = 2;
+    __device__ static float load(__amdgpu_buffer_rsrc_t r, int off) {
+        const unsigned h = __builtin_amdgcn_raw_buffer_load_b16(r, off, 0, 0);
+        return __uint_as_float(h << 16);
+    }
+};
+template <>
+struct Elem<CBCT_F16> {
+    static constexpr int size = 2;
+    __device__ static float load(__amdgpu_buffer_rsrc_t r, int off) {
+        const unsigned short h = __builtin_amdgcn_raw_buffer_load_b16(r, off, 0, 0);
+        return __half2float(__ushort_as_half(h));
+    }
+};
+
 // One x-y segment [aa, ab] of a row's walk: chords c0 (cell k) and c1 (cell
 // k + DIR), z-crossing update, then the next column's reads are issued before
 // this segment's products so their latency overlaps the arithmetic.
-template <int DIR, int MODE>
+template <int DIR, int MODE, int DT>
 struct FwdLane {
+    using E = Elem<DT>;
     float aa, an, pe, rg, cz, acc;
     int ob;           // byte offset of the lower cell read, from one cell below the column
     int obmax, nrec, Z, nz;
-    const float *vol_m;
+    const char *vol_m;
     unsigned cnt;
 
     __device__ __forceinline__ void step(int2 e, float lo, float hi, int2 enext, float &nlo,
@@ -116,19 +143,19 @@ struct FwdLane {
         const float c1 = ab - m;
         const float vcur = DIR > 0 ? lo : hi, vnext = DIR > 0 ? hi : lo;
         if constexpr (MODE == FWD_COUNT) {
-            const int kc = ob / 4 - (DIR > 0 ? 2 : 1);
+            const int kc = ob / E::size - (DIR > 0 ? 2 : 1);
             cnt += (c0 > 0.0f && kc >= 0 && kc < nz) ? 1u : 0u;
             cnt += (c1 > 0.0f && kc + DIR >= 0 && kc + DIR < nz) ? 1u : 0u;
         }
         if (an < ab) {
             pe += (float)DIR;
             an = plane_alpha(pe, rg, cz);
-            ob = DIR > 0 ? min(ob + 4, obmax) : max(ob - 4, 0);
+            ob = DIR > 0 ? min(ob + E::size, obmax) : max(ob - E::size, 0);
         }
         const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
-            (void *)(vol_m + (size_t)enext.y * Z), 0, nrec, kBufWord3);
-        nlo = ldb(rs, ob);
-        nhi = ldb(rs, ob + 4);
+            (void *)(vol_m + (size_t)enext.y * Z * E::size), 0, nrec, kBufWord3);
+        nlo = E::load(rs, ob);
+        nhi = E::load(rs, ob + E::size);
         if constexpr (MODE != FWD_COUNT) {
             acc = fmaf(c0, vcur, acc);
             acc = fmaf(c1, vnext, acc);
@@ -142,15 +169,17 @@ struct FwdLane {
 // the one-ahead reads never need to be copied (and waited for) early; with two
 // rows per lane the two walks share the segment stream and double the reads in
 // flight.
-template <int DIR, int MODE, int RPL>
-__device__ __forceinline__ void fwd_walk(const GeoK &G, const float *vol, const int2 *sp,
+template <int DIR, int MODE, int RPL, int DT>
+__device__ __forceinline__ void fwd_walk(const GeoK &G, const void *vol, const int2 *sp,
                                          int nseg, float a_in, const float4 *czr, float *acc,
                                          unsigned *cnt) {
-    FwdLane<DIR, MODE> L[RPL];
+    using E = Elem<DT>;
+    FwdLane<DIR, MODE, DT> L[RPL];
     float a0[RPL], a1[RPL], b0[RPL], b1[RPL];
     int2 e0 = sp[0], e1 = sp[1], e2 = sp[2];
+    const char *vol_m = (const char *)vol - E::size;
     const __amdgpu_buffer_rsrc_t rs0 = __builtin_amdgcn_make_buffer_rsrc(
-        (void *)(vol - 1 + (size_t)e0.y * G.Z), 0, (G.nz + 4) * 4, kBufWord3);
+        (void *)(vol_m + (size_t)e0.y * G.Z * E::size), 0, (G.nz + 4) * E::size, kBufWord3);
 #pragma unroll
     for (int p = 0; p < RPL; ++p) {
         int k;
@@ -160,14 +189,14 @@ __device__ __forceinline__ void fwd_walk(const GeoK &G, const float *vol, const 
         L[p].cz = czr[p].z;
         L[p].acc = 0.0f;
         L[p].cnt = 0;
-        L[p].ob = (k + (DIR > 0 ? 2 : 1)) * 4;
-        L[p].obmax = (G.nz + 2) * 4;
-        L[p].nrec = (G.nz + 4) * 4;
+        L[p].ob = (k + (DIR > 0 ? 2 : 1)) * E::size;
+        L[p].obmax = (G.nz + 2) * E::size;
+        L[p].nrec = (G.nz + 4) * E::size;
         L[p].Z = G.Z;
         L[p].nz = G.nz;
-        L[p].vol_m = vol - 1;
-        a0[p] = ldb(rs0, L[p].ob);
-        a1[p] = ldb(rs0, L[p].ob + 4);
+        L[p].vol_m = vol_m;
+        a0[p] = E::load(rs0, L[p].ob);
+        a1[p] = E::load(rs0, L[p].ob + E::size);
     }
     // Entries past the last segment are no-op segments (zero length, exit
     // parameter, column 0), so the walk runs in whole pairs and reads table
@@ -193,7 +222,7 @@ __device__ __forceinline__ void fwd_walk(const GeoK &G, const float *vol, const 
 // least 128 rows.
 __host__ __device__ inline int fwd_rpl(int nv) { return nv / 2 >= 128 ? 2 : 1; }
 
-template <int MODE, int RPL>
+template <int MODE, int RPL, int DT>
 __global__ void __launch_bounds__(256)
 k_fwd(GeoK G, FwdArgs a) {
     if constexpr (MODE == FWD_SOLVER) {
@@ -240,9 +269,9 @@ k_fwd(GeoK G, FwdArgs a) {
     if (nseg > 0) {
         const float a_in = __int_as_float(hdr.x);
         if (up)
-            fwd_walk<1, MODE, RPL>(G, a.vol, sp, nseg, a_in, czr, acc, cnt);
+            fwd_walk<1, MODE, RPL, DT>(G, a.vol, sp, nseg, a_in, czr, acc, cnt);
         else
-            fwd_walk<-1, MODE, RPL>(G, a.vol, sp, nseg, a_in, czr, acc, cnt);
+            fwd_walk<-1, MODE, RPL, DT>(G, a.vol, sp, nseg, a_in, czr, acc, cnt);
     }
 
     if constexpr (MODE == FWD_COUNT) {
@@ -259,7 +288,7 @@ k_fwd(GeoK G, FwdArgs a) {
         const size_t o = ((size_t)view * G.nu + iuc) * G.nv + ivc[p];
         const float L2 = G.Lu2[iuc] + G.Lv2[ivc[p]];
         if constexpr (MODE == FWD_PLAIN) {
-            if (ok) a.out[o] = sqrtf(L2) * acc[p];
+            if (ok) a.out[o] = sqrtf(L2) * acc[p] * a.scale;
         } else {
             // u-hat = L * u, u = s1 * (A v) + s2 * u_old  =>  u-hat = s1 L^2 acc + s2 u-hat_old
             const float s1 = (float)*a.s1, s2 = (float)*a.s2;
@@ -287,25 +316,37 @@ int64_t forward_blocks(const GeoK &G) {
     return (int64_t)G.nviews * nrb * ((G.nu + 3) / 4);
 }
 
-template <int RPL>
+template <int RPL, int DT>
 static void launch_forward_rpl(const GeoK &G, int mode, const FwdArgs &a, hipStream_t s,
                                dim3 grid) {
     const dim3 block(256);
     if (mode == FWD_PLAIN)
-        hipLaunchKernelGGL((k_fwd<FWD_PLAIN, RPL>), grid, block, 0, s, G, a);
+        hipLaunchKernelGGL((k_fwd<FWD_PLAIN, RPL, DT>), grid, block, 0, s, G, a);
     else if (mode == FWD_SOLVER)
-        hipLaunchKernelGGL((k_fwd<FWD_SOLVER, RPL>), grid, block, 0, s, G, a);
+        hipLaunchKernelGGL((k_fwd<FWD_SOLVER, RPL, DT>), grid, block, 0, s, G, a);
     else
-        hipLaunchKernelGGL((k_fwd<FWD_COUNT, RPL>), grid, block, 0, s, G, a);
+        hipLaunchKernelGGL((k_fwd<FWD_COUNT, RPL, DT>), grid, block, 0, s, G, a);
 }
 
-void launch_forward(const GeoK &G, int mode, const FwdArgs &a, hipStream_t s) {
+template <int DT>
+static void launch_forward_dt(const GeoK &G, int mode, const FwdArgs &a, hipStream_t s,
+                              dim3 grid) {
+    if (fwd_rpl(G.nv) == 2)
+        launch_forward_rpl<2, DT>(G, mode, a, s, grid);
+    else
+        launch_forward_rpl<1, DT>(G, mode, a, s, grid);
+}
+
+void launch_forward(const GeoK &G, int mode, const FwdArgs &a, hipStream_t s, int dtype) {
     const int64_t nb = forward_blocks(G);
     if (nb > 0x7fffffff) throw Error(CBCT_ERR_INVALID, "forward grid too large");
-    if (fwd_rpl(G.nv) == 2)
-        launch_forward_rpl<2>(G, mode, a, s, dim3((unsigned)nb));
+    const dim3 grid((unsigned)nb);
+    if (dtype == CBCT_BF16)
+        launch_forward_dt<CBCT_BF16>(G, mode, a, s, grid);
+    else if (dtype == CBCT_F16)
+        launch_forward_dt<CBCT_F16>(G, mode, a, s, grid);
     else
-        launch_forward_rpl<1>(G, mode, a, s, dim3((unsigned)nb));
+        launch_forward_dt<CBCT_F32>(G, mode, a, s, grid);
     CBCT_HIP(hipGetLastError());
 }
 
@@ -482,19 +523,22 @@ void launch_back(const GeoK &G, const float *yhat, float *out, const int *brk, h
 
 // ---------------------------------------------------------------- layout kernels
 
+template <typename T>
 __global__ void __launch_bounds__(256)
-k_transpose(const float *__restrict__ in, float *__restrict__ out, int R, int C, int64_t ib,
+k_transpose(const T *__restrict__ in, T *__restrict__ out, int R, int C, int64_t ib,
             int64_t ir, int64_t ioff, int64_t ob, int64_t oc, int64_t ooff,
             const float *__restrict__ Lu2, const float *__restrict__ Lv2) {
-    __shared__ float tile[32][33];
+    __shared__ T tile[32][33];
     const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8
     const int bc = blockIdx.x, br = blockIdx.y, bb = blockIdx.z;
     const int64_t ibase = (int64_t)bb * ib + ioff, obase = (int64_t)bb * ob + ooff;
     for (int q = ty; q < 32; q += 8) {
         const int r = br * 32 + q, c = bc * 32 + tx;
         if (r < R && c < C) {
-            float v = in[ibase + (int64_t)r * ir + c];
-            if (Lu2) v *= sqrtf(Lu2[c] + Lv2[r]);
+            T v = in[ibase + (int64_t)r * ir + c];
+            if constexpr (sizeof(T) == 4) {
+                if (Lu2) v *= sqrtf(Lu2[c] + Lv2[r]);
+            }
             tile[q][tx] = v;
         }
     }
@@ -509,8 +553,18 @@ void launch_transpose(const float *in, float *out, int B, int R, int C, int64_t 
                       int64_t ioff, int64_t ob, int64_t oc, int64_t ooff, const float *Lu2,
                       const float *Lv2, hipStream_t s) {
     dim3 grid((unsigned)((C + 31) / 32), (unsigned)((R + 31) / 32), (unsigned)B);
-    hipLaunchKernelGGL(k_transpose, grid, dim3(256), 0, s, in, out, R, C, ib, ir, ioff, ob, oc,
-                       ooff, Lu2, Lv2);
+    hipLaunchKernelGGL(k_transpose<float>, grid, dim3(256), 0, s, in, out, R, C, ib, ir, ioff, ob,
+                       oc, ooff, Lu2, Lv2);
+    CBCT_HIP(hipGetLastError());
+}
+
+// 16-bit x[k][j][i] -> 16-bit column volume (pads untouched).
+static void vol_to_cols16(const GeoK &G, const unsigned short *x, unsigned short *cols,
+                          hipStream_t s) {
+    dim3 grid((unsigned)((G.nx + 31) / 32), (unsigned)((G.nz + 31) / 32), (unsigned)G.ny);
+    hipLaunchKernelGGL(k_transpose<unsigned short>, grid, dim3(256), 0, s, x, cols, G.nz, G.nx,
+                       (int64_t)G.nx, (int64_t)G.nx * G.ny, (int64_t)0, (int64_t)G.nx * G.Z,
+                       (int64_t)G.Z, (int64_t)1, (const float *)nullptr, (const float *)nullptr);
     CBCT_HIP(hipGetLastError());
 }
 
@@ -625,22 +679,26 @@ int cbct_forward(const cbct_geom *gc, const void *x, cbct_dtype xt, float x_scal
         cbct_geom *g = const_cast<cbct_geom *>(gc);
         hipStream_t s = (hipStream_t)hip_stream;
         GeoK G = geo_for_device(g);
-        const int64_t M = g->n_vox(), N = g->n_proj();
-        StreamBuf cols(sizeof(float) * g->pad_floats(), s);
+        const int64_t N = g->n_proj();
+        const size_t es = xt == CBCT_F32 ? 4 : 2;
+        // padded column copy in the input's own storage type; the kernel widens
+        // 16-bit values on load and applies x_scale in its epilogue
+        StreamBuf cols(es * (size_t)g->pad_floats(), s);
         StreamBuf ycol(sizeof(float) * N, s);
-        float *P = cols.f() + kGuard;
-        launch_fill(cols.f(), g->pad_floats(), 0.0f, s);
-        const float *xf = (const float *)x;
-        StreamBuf conv(xt == CBCT_F32 && x_scale == 1.0f ? 0 : sizeof(float) * M, s);
-        if (!(xt == CBCT_F32 && x_scale == 1.0f)) {
-            to_f32(x, xt, x_scale, conv.f(), M, s);
-            xf = conv.f();
-        }
-        vol_to_cols(G, xf, P, s);
+        launch_fill(cols.f(), (int64_t)(es * (size_t)g->pad_floats() / 4), 0.0f, s);
         FwdArgs a{};
-        a.vol = P;
+        if (xt == CBCT_F32) {
+            float *P = cols.f() + kGuard;
+            vol_to_cols(G, (const float *)x, P, s);
+            a.vol = P;
+        } else {
+            unsigned short *P = (unsigned short *)cols.p + kGuard;
+            vol_to_cols16(G, (const unsigned short *)x, P, s);
+            a.vol = P;
+        }
         a.out = ycol.f();
-        launch_forward(G, FWD_PLAIN, a, s);
+        a.scale = x_scale;
+        launch_forward(G, FWD_PLAIN, a, s, xt);
         cols_to_proj(G, ycol.f(), y, s);
         return CBCT_OK;
     } catch (const std::exception &e) {
@@ -754,6 +812,7 @@ int cbct_forward_cols(const cbct_geom *gc, const float *cols, float *ycols, void
         FwdArgs a{};
         a.vol = cols + kGuard;
         a.out = ycols;
+        a.scale = 1.0f;
         launch_forward(G, FWD_PLAIN, a, (hipStream_t)hip_stream);
         return CBCT_OK;
     } catch (const std::exception &e) {

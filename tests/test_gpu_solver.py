@@ -133,3 +133,33 @@ def test_odd_geometry_solve(orc, lib):
     ref = orc.irn_piccs(og, b, xp, xp, 0.5, 1.5, 0.2, 2, 4)
     xg, rep = _gpu_solve(lib, d, b, xp, xp, lib.SolveParams(0.5, 1.5, 0.2, 2, 4))
     assert rel(xg, ref.x) <= SOLVE_TOL
+
+
+@pytest.mark.parametrize("prec", ["bf16", "f16"])
+def test_mixed_precision_solve_within_1e3_of_fp64(orc, lib, prec):
+    """16-bit projector operand, fp32 accumulation, fp64 Krylov scalars: <= 1e-3 vs FP64."""
+    d, og, prior, cur, b, sp = c1_inputs(orc)
+    ref = orc.irn_piccs(og, b, prior, prior, sp["alpha"], sp["lam"], sp["tau"], sp["n_outer"],
+                        sp["n_inner"])
+    pr = lib.PREC_MIXED_BF16 if prec == "bf16" else lib.PREC_MIXED_F16
+    p = lib.SolveParams(sp["alpha"], sp["lam"], sp["tau"], sp["n_outer"], sp["n_inner"],
+                        precision=pr)
+    xg, rep = _gpu_solve(lib, d, b, prior, prior, p)
+    err = rel(xg, ref.x)
+    print(f"{prec}: rel L2 vs FP64 oracle {err:.2e}")
+    assert err <= 1e-3
+    assert rep["inner_done"] == sp["n_outer"] * sp["n_inner"]
+
+
+def test_mixed_forms_on_ragged_geometry(orc, lib):
+    rng = np.random.default_rng(19)
+    d = dict(nx=21, ny=19, nz=17, vx=1.0, vy=1.0, vz=1.0, nu=37, nv=150, du=1.1, dv=0.45,
+             dso=80.0, dsd=130.0, n_views=13)
+    og = orc.Geometry.from_dict(d)
+    xp = rng.uniform(size=og.vol_shape).astype(np.float32).astype(np.float64)
+    xt = xp + 0.3 * (rng.uniform(size=og.vol_shape) > 0.9)
+    b = orc.forward(og, xt).astype(np.float32).astype(np.float64)
+    ref = orc.irn_piccs(og, b, xp, xp, 0.5, 1.5, 0.2, 2, 4)
+    for pr in (lib.PREC_MIXED_BF16, lib.PREC_MIXED_F16):
+        xg, _ = _gpu_solve(lib, d, b, xp, xp, lib.SolveParams(0.5, 1.5, 0.2, 2, 4, precision=pr))
+        assert rel(xg, ref.x) <= 1e-3
