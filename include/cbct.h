@@ -203,6 +203,102 @@ int piccs_krylov_solve(const cbct_geom *g, const float *b, const float *xp, floa
                        const piccs_params *p, void *workspace, size_t ws_bytes,
                        piccs_report *rep, void *hip_stream);
 
+/* ------------------------------------------------------------------------ */
+/* Serving: continuous batching of repeated-scan reconstructions             */
+/*
+ * The paper motivates the method by repeated scans of one patient during an
+ * intervention, each reconstructed from few views against a prior image
+ * (Sec. 1 and Sec. 2.2.2).  A server runs such requests for many patients on
+ * one device:
+ *  - every request is one IRN-PICCS solve (piccs_krylov_solve) of its own
+ *    geometry and parameters against its patient's prior;
+ *  - each patient's prior x_p and previous reconstruction x_prev stay
+ *    resident on the device; a request starts from x_prev (warm start) or
+ *    from x_p;
+ *  - requests are admitted in arrival order as stream slots and HBM budget
+ *    free up, and admitted requests run concurrently on their own streams;
+ *    requests of one patient run one at a time in arrival order;
+ *  - the budget covers everything the server places on the device: residents
+ *    (8 bytes per voxel per patient), cached projector tables of each
+ *    geometry, and per running request b, x and the solve workspace.
+ * All server calls are thread-safe.  Times are seconds on a monotonic clock
+ * since cbct_server_create.
+ */
+typedef struct {
+    size_t hbm_budget_bytes; /* device memory the server may use; 0 = 90 % of free  */
+    int32_t max_slots;       /* concurrent requests on the device (streams), >= 1    */
+    int32_t device;          /* HIP device ordinal                                   */
+    int32_t max_queue;       /* waiting requests before CBCT_ERR_BUSY; 0 = 4096      */
+} cbct_server_config;
+
+typedef struct cbct_server cbct_server;
+
+typedef enum {
+    CBCT_X0_PREVIOUS = 0, /* start from the patient's last reconstruction, else x_p */
+    CBCT_X0_PRIOR = 1     /* start from x_p                                          */
+} cbct_x0_source;
+
+typedef struct {
+    int32_t patient;       /* id given to cbct_server_add_prior                     */
+    cbct_geom_desc geom;   /* scan geometry; its volume must be the patient's       */
+    const float *b_host;   /* HOST projections b[view][v][u]; copied at submit      */
+    piccs_params params;   /* solve parameters (reorth must be 0)                   */
+    int32_t x0;            /* cbct_x0_source                                        */
+} cbct_request;
+
+typedef struct {
+    int32_t status;        /* CBCT_OK or the request's error                         */
+    double t_submit;       /* submit returned                                        */
+    double t_admit;        /* admitted: its work was enqueued on the device          */
+    double t_done;         /* result ready to poll                                   */
+    piccs_report report;   /* set report.resid_hist (HOST, n_outer*n_inner) before
+                              polling to receive the residual history               */
+} cbct_result;
+
+typedef struct {
+    int64_t capacity, used, peak_used, resident; /* bytes of the HBM budget          */
+    int64_t queued, in_flight, peak_in_flight, done_unpolled;
+    int64_t completed, failed, geom_placements, geom_evictions;
+} cbct_server_stats;
+
+/* Reserves the budget on the device and starts the scheduler thread.
+ * Errors: CBCT_ERR_INVALID (max_slots < 1, bad device), CBCT_ERR_OOM. */
+int cbct_server_create(const cbct_server_config *c, cbct_server **out);
+
+/* Registers patient `patient` with prior image xp_host[z][y][x] (HOST, copied;
+ * the call returns once it is on the device).  The volume of g is the
+ * patient's volume.  Errors: CBCT_ERR_INVALID (bad geometry, id already
+ * registered), CBCT_ERR_OOM (residents do not fit in the budget). */
+int cbct_server_add_prior(cbct_server *s, int32_t patient, const cbct_geom_desc *g,
+                          const float *xp_host);
+
+/* Queues a request and returns at once with its ticket (> 0).  Errors:
+ * CBCT_ERR_INVALID (geometry, volume mismatch, params), CBCT_ERR_NOT_FOUND
+ * (unknown patient), CBCT_ERR_BUSY (queue full), CBCT_ERR_OOM (the request
+ * cannot fit beside the residents even on an idle device). */
+int cbct_server_submit(cbct_server *s, const cbct_request *r, uint64_t *ticket);
+
+/* Non-blocking.  CBCT_PENDING while the request is queued or running;
+ * CBCT_ERR_NOT_FOUND for an unknown or already collected ticket.  Once
+ * finished, copies x[z][y][x] into x_host_out (HOST, may be NULL), fills *res
+ * (may be NULL), forgets the ticket and returns the request's status. */
+int cbct_server_poll(cbct_server *s, uint64_t ticket, float *x_host_out, cbct_result *res);
+
+/* Device bytes the server needs (host-only computation, no device access):
+ * *request_bytes while a request of this geometry and params runs (b, x and
+ * the solve workspace), *tables_bytes for the geometry's cached projector
+ * tables, *resident_bytes per patient of this volume (x_p and x_prev).  Any
+ * output pointer may be NULL.  Errors: CBCT_ERR_INVALID. */
+int cbct_server_footprint(const cbct_geom_desc *g, const piccs_params *p, size_t *request_bytes,
+                          size_t *tables_bytes, size_t *resident_bytes);
+
+/* Snapshot of the scheduler's counters. */
+int cbct_server_stats_get(cbct_server *s, cbct_server_stats *out);
+
+/* Waits for every queued and running request to finish, then releases the
+ * device memory, streams and thread.  Results never polled are dropped. */
+int cbct_server_destroy(cbct_server *s);
+
 #ifdef __cplusplus
 }
 #endif

@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 LIB = os.path.join(HERE, "libcbct.so")
-SOURCES = ["geom.cpp", "proj.hip", "piccs.hip"]
+SOURCES = ["geom.cpp", "proj.hip", "piccs.hip", "server.cpp"]
 ARCH = os.environ.get("CBCT_OFFLOAD_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
@@ -41,6 +41,22 @@ def _compile(src: str, outdir: str, verbose: bool) -> str:
     return obj
 
 
+SIM_LIB = os.path.join(HERE, "libcbct_sim.so")
+
+
+def build_sim(verbose: bool = False) -> str:
+    """Host-only library driving the server's scheduling core with a simulated
+    device (tests of admission and residency without a GPU)."""
+    tmp = SIM_LIB + ".tmp"
+    cmd = [os.environ.get("CXX", "g++"), "-O2", "-std=c++17", "-fPIC", "-shared", "-Wall",
+           f"-I{INCLUDE}", os.path.join(CSRC, "serve_sim.cpp"), "-o", tmp]
+    if verbose:
+        print(" ".join(cmd), file=sys.stderr)
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, SIM_LIB)
+    return SIM_LIB
+
+
 def build(verbose: bool = False) -> str:
     outdir = os.path.join(HERE, "_build")
     os.makedirs(outdir, exist_ok=True)
@@ -52,6 +68,7 @@ def build(verbose: bool = False) -> str:
         print(" ".join(cmd), file=sys.stderr)
     subprocess.run(cmd, check=True)
     os.replace(tmp, LIB)
+    build_sim(verbose)
     return LIB
 
 

@@ -31,7 +31,9 @@ EXPORTS = ["cbct_last_error", "cbct_geom_create", "cbct_geom_destroy", "cbct_geo
            "cbct_geom_nnz", "cbct_forward", "cbct_back", "piccs_weights",
            "piccs_workspace_bytes", "piccs_krylov_solve", "cbct_col_sizes", "cbct_vol_to_cols",
            "cbct_cols_to_vol", "cbct_proj_to_cols", "cbct_cols_to_proj", "cbct_forward_cols",
-           "cbct_back_cols"]
+           "cbct_back_cols", "cbct_server_create", "cbct_server_add_prior", "cbct_server_submit",
+           "cbct_server_poll", "cbct_server_stats_get", "cbct_server_destroy",
+           "cbct_server_footprint"]
 
 
 class GeomDesc(ctypes.Structure):
@@ -306,3 +308,161 @@ def forward_cols(g: Geometry, cols, ycols, stream=None):
 def back_cols(g: Geometry, ywcols, cols, stream=None):
     _check(_lib.cbct_back_cols(g.handle, _ptr(ywcols), _ptr(cols), _stream(stream)))
     return cols
+
+
+# ---------------------------------------------------------------- serving
+
+X0_PREVIOUS, X0_PRIOR = 0, 1
+
+
+class ServerConfig(ctypes.Structure):
+    _fields_ = [("hbm_budget_bytes", ctypes.c_size_t), ("max_slots", ctypes.c_int32),
+                ("device", ctypes.c_int32), ("max_queue", ctypes.c_int32)]
+
+
+class Request(ctypes.Structure):
+    _fields_ = [("patient", ctypes.c_int32), ("geom", GeomDesc),
+                ("b_host", ctypes.POINTER(ctypes.c_float)), ("params", Params),
+                ("x0", ctypes.c_int32)]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("t_submit", ctypes.c_double),
+                ("t_admit", ctypes.c_double), ("t_done", ctypes.c_double),
+                ("report", Report)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int64) for n in (
+        "capacity", "used", "peak_used", "resident", "queued", "in_flight", "peak_in_flight",
+        "done_unpolled", "completed", "failed", "geom_placements", "geom_evictions")]
+
+
+_lib.cbct_server_create.argtypes = [ctypes.POINTER(ServerConfig), ctypes.POINTER(_vp)]
+_lib.cbct_server_add_prior.argtypes = [_vp, ctypes.c_int32, ctypes.POINTER(GeomDesc), _vp]
+_lib.cbct_server_submit.argtypes = [_vp, ctypes.POINTER(Request),
+                                    ctypes.POINTER(ctypes.c_uint64)]
+_lib.cbct_server_poll.argtypes = [_vp, ctypes.c_uint64, _vp, ctypes.POINTER(Result)]
+_lib.cbct_server_stats_get.argtypes = [_vp, ctypes.POINTER(ServerStats)]
+_lib.cbct_server_destroy.argtypes = [_vp]
+_szp = ctypes.POINTER(ctypes.c_size_t)
+_lib.cbct_server_footprint.argtypes = [ctypes.POINTER(GeomDesc), ctypes.POINTER(Params), _szp,
+                                       _szp, _szp]
+
+
+def server_footprint(geom: dict, params: SolveParams) -> dict:
+    """Device bytes per running request, per cached geometry and per patient."""
+    desc, _keep = _desc(geom)
+    cp = params.c()
+    r, t, p = ctypes.c_size_t(), ctypes.c_size_t(), ctypes.c_size_t()
+    _check(_lib.cbct_server_footprint(ctypes.byref(desc), ctypes.byref(cp), ctypes.byref(r),
+                                      ctypes.byref(t), ctypes.byref(p)))
+    return {"request": r.value, "tables": t.value, "resident": p.value}
+
+
+def _desc(d):
+    """GeomDesc from a geometry dict; returns (desc, keep-alive angles array)."""
+    keys = ("nx", "ny", "nz", "vx", "vy", "vz", "nu", "nv", "du", "dv", "dso", "dsd", "n_views")
+    desc = GeomDesc(*[d[k] for k in keys], None)
+    arr = None
+    if d.get("angles") is not None:
+        arr = (ctypes.c_double * d["n_views"])(*[float(a) for a in d["angles"]])
+        desc.angles = ctypes.cast(arr, ctypes.POINTER(ctypes.c_double))
+    return desc, arr
+
+
+def _host_f32(a, n):
+    import numpy as np
+    a = np.ascontiguousarray(a, dtype=np.float32)
+    if a.size != n:
+        raise ValueError(f"expected {n} elements, got {a.size}")
+    return a
+
+
+class Server:
+    """cbct_server_*: continuous batching of IRN-PICCS requests on one device.
+
+    Host arrays are numpy float32 (copied by the library at submit / add_prior).
+    """
+
+    def __init__(self, hbm_budget_bytes=0, max_slots=4, device=0, max_queue=0):
+        cfg = ServerConfig(hbm_budget_bytes, max_slots, device, max_queue)
+        h = _vp()
+        _check(_lib.cbct_server_create(ctypes.byref(cfg), ctypes.byref(h)))
+        self.handle = h
+        self._nvox = {}
+
+    def add_prior(self, patient: int, geom: dict, xp):
+        desc, _keep = _desc(geom)
+        n = geom["nx"] * geom["ny"] * geom["nz"]
+        a = _host_f32(xp, n)
+        _check(_lib.cbct_server_add_prior(self.handle, patient, ctypes.byref(desc),
+                                          ctypes.c_void_p(a.ctypes.data)))
+        self._nvox[patient] = n
+
+    def submit(self, patient: int, geom: dict, b, params: SolveParams, x0=X0_PREVIOUS) -> int:
+        """Returns the ticket; raises CbctError (code ERR_BUSY / ERR_OOM / ...) on refusal."""
+        desc, _keep = _desc(geom)
+        n = geom["n_views"] * geom["nu"] * geom["nv"]
+        a = _host_f32(b, n)
+        req = Request(patient, desc, a.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
+                      params.c(), x0)
+        t = ctypes.c_uint64()
+        _check(_lib.cbct_server_submit(self.handle, ctypes.byref(req), ctypes.byref(t)))
+        return t.value
+
+    def poll(self, ticket: int, out=None, hist_len: int = 0):
+        """Returns None while pending; else (status, x or None, result dict)."""
+        res = Result()
+        hist = None
+        if hist_len:
+            hist = (ctypes.c_double * hist_len)()
+            res.report.resid_hist = ctypes.cast(hist, ctypes.POINTER(ctypes.c_double))
+        rc = _lib.cbct_server_poll(self.handle, ticket,
+                                   ctypes.c_void_p(out.ctypes.data) if out is not None else None,
+                                   ctypes.byref(res))
+        if rc == PENDING:
+            return None
+        if rc == ERR_NOT_FOUND:  # unknown or already collected ticket
+            raise CbctError(rc, last_error())
+        info = {"status": res.status, "t_submit": res.t_submit, "t_admit": res.t_admit,
+                "t_done": res.t_done, "inner_done": res.report.inner_done,
+                "outer_done": res.report.outer_done, "breakdown": res.report.breakdown,
+                "error": last_error() if rc != OK else ""}
+        if hist is not None:
+            info["phibar"] = list(hist)
+        return rc, out, info
+
+    def wait(self, ticket: int, out=None, hist_len: int = 0, timeout: float = 120.0,
+             interval: float = 2e-4):
+        import time
+        t_end = time.monotonic() + timeout
+        while True:
+            r = self.poll(ticket, out, hist_len)
+            if r is not None:
+                return r
+            if time.monotonic() > t_end:
+                raise TimeoutError(f"ticket {ticket} not done after {timeout} s")
+            time.sleep(interval)
+
+    def stats(self) -> dict:
+        st = ServerStats()
+        _check(_lib.cbct_server_stats_get(self.handle, ctypes.byref(st)))
+        return {n: getattr(st, n) for n, _ in ServerStats._fields_}
+
+    def close(self):
+        if getattr(self, "handle", None):
+            h, self.handle = self.handle, None
+            _check(_lib.cbct_server_destroy(h))
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -114,6 +114,61 @@ static GeoK make_geok(const cbct_geom *g, const DevTables &t) {
     return G;
 }
 
+// Offsets of the device tables inside one block, each part 256-byte aligned.
+struct TableLayout {
+    size_t xy, xy0, zr, Lu2, Lv2, trig, seghdr, seg, total;
+};
+
+static TableLayout table_layout(const cbct_geom_desc &d) {
+    const size_t nr = (size_t)d.n_views * d.nu;
+    const size_t stride = (size_t)d.nx + d.ny - 1 + kSegPad;
+    TableLayout L{};
+    size_t o = 0;
+    auto put = [&](size_t bytes) {
+        const size_t at = o;
+        o += (bytes + 255) & ~(size_t)255;
+        return at;
+    };
+    L.xy = put(sizeof(float4) * nr);
+    L.xy0 = put(sizeof(float2) * nr);
+    L.zr = put(sizeof(float4) * d.nv);
+    L.Lu2 = put(sizeof(float) * d.nu);
+    L.Lv2 = put(sizeof(float) * d.nv);
+    L.trig = put(sizeof(float2) * d.n_views);
+    L.seghdr = put(sizeof(int2) * nr);
+    L.seg = put(sizeof(int2) * nr * stride);
+    L.total = o;
+    return L;
+}
+
+// Points t into `base` and enqueues the table uploads and the segment-table
+// build on s.  The host tables live as long as g.
+static void upload_tables(cbct_geom *g, char *base, DevTables &t, hipStream_t s) {
+    const cbct_geom_desc &d = g->d;
+    const TableLayout L = table_layout(d);
+    t.block = base;
+    t.xy = (float4 *)(base + L.xy);
+    t.xy0 = (float2 *)(base + L.xy0);
+    t.zr = (float4 *)(base + L.zr);
+    t.Lu2 = (float *)(base + L.Lu2);
+    t.Lv2 = (float *)(base + L.Lv2);
+    t.trig = (float2 *)(base + L.trig);
+    t.seghdr = (int2 *)(base + L.seghdr);
+    t.seg = (int2 *)(base + L.seg);
+    CBCT_HIP(hipMemcpyAsync(t.xy, g->xy.data(), sizeof(float4) * g->xy.size(),
+                            hipMemcpyHostToDevice, s));
+    CBCT_HIP(hipMemcpyAsync(t.xy0, g->xy0.data(), sizeof(float2) * g->xy0.size(),
+                            hipMemcpyHostToDevice, s));
+    CBCT_HIP(hipMemcpyAsync(t.zr, g->zr.data(), sizeof(float4) * g->zr.size(),
+                            hipMemcpyHostToDevice, s));
+    CBCT_HIP(hipMemcpyAsync(t.Lu2, g->Lu2.data(), sizeof(float) * d.nu, hipMemcpyHostToDevice, s));
+    CBCT_HIP(hipMemcpyAsync(t.Lv2, g->Lv2.data(), sizeof(float) * d.nv, hipMemcpyHostToDevice, s));
+    CBCT_HIP(hipMemcpyAsync(t.trig, g->trig.data(), sizeof(float2) * g->trig.size(),
+                            hipMemcpyHostToDevice, s));
+    GeoK G = make_geok(g, t);
+    launch_segment_tables(G, t.seghdr, t.seg, s);
+}
+
 GeoK geo_for_device(cbct_geom *g) {
     int dev = 0;
     CBCT_HIP(hipGetDevice(&dev));
@@ -122,36 +177,18 @@ GeoK geo_for_device(cbct_geom *g) {
         std::lock_guard<std::mutex> lk(g->mu);
         auto it = g->dev.find(dev);
         if (it == g->dev.end()) {
-            const cbct_geom_desc &d = g->d;
+            void *block = nullptr;
+            hipStream_t s = nullptr;
             try {
-                CBCT_HIP(hipMalloc(&t.xy, sizeof(float4) * g->xy.size()));
-                CBCT_HIP(hipMalloc(&t.xy0, sizeof(float2) * g->xy0.size()));
-                CBCT_HIP(hipMalloc(&t.zr, sizeof(float4) * g->zr.size()));
-                CBCT_HIP(hipMalloc(&t.Lu2, sizeof(float) * g->Lu2.size()));
-                CBCT_HIP(hipMalloc(&t.Lv2, sizeof(float) * g->Lv2.size()));
-                CBCT_HIP(hipMalloc(&t.trig, sizeof(float2) * g->trig.size()));
-                CBCT_HIP(hipMemcpy(t.xy, g->xy.data(), sizeof(float4) * g->xy.size(),
-                                   hipMemcpyHostToDevice));
-                CBCT_HIP(hipMemcpy(t.xy0, g->xy0.data(), sizeof(float2) * g->xy0.size(),
-                                   hipMemcpyHostToDevice));
-                CBCT_HIP(hipMemcpy(t.zr, g->zr.data(), sizeof(float4) * g->zr.size(),
-                                   hipMemcpyHostToDevice));
-                CBCT_HIP(hipMemcpy(t.Lu2, g->Lu2.data(), sizeof(float) * d.nu,
-                                   hipMemcpyHostToDevice));
-                CBCT_HIP(hipMemcpy(t.Lv2, g->Lv2.data(), sizeof(float) * d.nv,
-                                   hipMemcpyHostToDevice));
-                CBCT_HIP(hipMemcpy(t.trig, g->trig.data(), sizeof(float2) * g->trig.size(),
-                                   hipMemcpyHostToDevice));
-                const size_t nr = (size_t)d.n_views * d.nu;
-                const size_t stride = (size_t)d.nx + d.ny - 1 + kSegPad;
-                CBCT_HIP(hipMalloc(&t.seghdr, sizeof(int2) * nr));
-                CBCT_HIP(hipMalloc(&t.seg, sizeof(int2) * nr * stride));
-                GeoK G = make_geok(g, t);
-                build_segment_tables(G, t.seghdr, t.seg);
+                CBCT_HIP(hipMalloc(&block, table_layout(g->d).total));
+                CBCT_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+                upload_tables(g, (char *)block, t, s);
+                CBCT_HIP(hipStreamSynchronize(s));
+                CBCT_HIP(hipStreamDestroy(s));
+                s = nullptr;
             } catch (...) {
-                (void)hipFree(t.xy); (void)hipFree(t.xy0); (void)hipFree(t.zr); (void)hipFree(t.Lu2);
-                (void)hipFree(t.Lv2); (void)hipFree(t.trig); (void)hipFree(t.seghdr);
-                (void)hipFree(t.seg);
+                if (s) (void)hipStreamDestroy(s);
+                (void)hipFree(block);
                 throw;
             }
             g->dev[dev] = t;
@@ -162,12 +199,27 @@ GeoK geo_for_device(cbct_geom *g) {
     return make_geok(g, t);
 }
 
-size_t geom_table_bytes(const cbct_geom_desc &d) {
-    const size_t nr = (size_t)d.n_views * d.nu;
-    return nr * (sizeof(float4) + sizeof(float2) + sizeof(int2) * ((size_t)d.nx + d.ny + kSegPad)) +
-           (size_t)d.nv * (sizeof(float4) + sizeof(float)) + (size_t)d.nu * sizeof(float) +
-           (size_t)d.n_views * sizeof(float2);
+void geo_place(cbct_geom *g, void *mem, hipStream_t s) {
+    CBCT_REQUIRE(mem && ((uintptr_t)mem & 255) == 0, "table memory must be 256-byte aligned");
+    int dev = 0;
+    CBCT_HIP(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lk(g->mu);
+    CBCT_REQUIRE(g->dev.find(dev) == g->dev.end(), "geometry already has device tables");
+    DevTables t;
+    upload_tables(g, (char *)mem, t, s);
+    t.external = true;
+    g->dev[dev] = t;
 }
+
+void geo_unplace(cbct_geom *g) {
+    int dev = 0;
+    CBCT_HIP(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lk(g->mu);
+    auto it = g->dev.find(dev);
+    if (it != g->dev.end() && it->second.external) g->dev.erase(it);
+}
+
+size_t geom_table_bytes(const cbct_geom_desc &d) { return table_layout(d).total; }
 
 }  // namespace cbct
 
@@ -209,15 +261,9 @@ void cbct_geom_destroy(cbct_geom *g) {
     int cur = 0;
     (void)hipGetDevice(&cur);
     for (auto &kv : g->dev) {
+        if (kv.second.external) continue;
         (void)hipSetDevice(kv.first);
-        (void)hipFree(kv.second.xy);
-        (void)hipFree(kv.second.xy0);
-        (void)hipFree(kv.second.zr);
-        (void)hipFree(kv.second.Lu2);
-        (void)hipFree(kv.second.Lv2);
-        (void)hipFree(kv.second.trig);
-        (void)hipFree(kv.second.seghdr);
-        (void)hipFree(kv.second.seg);
+        (void)hipFree(kv.second.block);
     }
     (void)hipSetDevice(cur);
     delete g;

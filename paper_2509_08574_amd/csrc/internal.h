@@ -80,6 +80,8 @@ struct DevTables {
     float2 *trig = nullptr;
     int2 *seghdr = nullptr;
     int2 *seg = nullptr;
+    void *block = nullptr;   // one allocation holding all of the above
+    bool external = false;   // block owned by the caller of geo_place
 };
 
 }  // namespace cbct
@@ -109,10 +111,28 @@ namespace cbct {
 // Kernel arguments for geometry g on the current device (uploads tables and
 // builds the segment tables once per device).
 GeoK geo_for_device(cbct_geom *g);
-// Builds the x-y segment tables of G (seghdr/seg must be allocated); synchronous.
-void build_segment_tables(const GeoK &G, int2 *seghdr, int2 *seg);
-// Bytes of device memory held per device by the geometry's tables.
+// Enqueues the build of the x-y segment tables of G on s (seghdr/seg allocated).
+void launch_segment_tables(const GeoK &G, int2 *seghdr, int2 *seg, hipStream_t s);
+// Bytes of device memory held per device by the geometry's tables (one block).
 size_t geom_table_bytes(const cbct_geom_desc &d);
+// Places the current device's tables of g in caller memory `mem` (256-byte
+// aligned, geom_table_bytes bytes), enqueuing the upload and the segment-table
+// build on s; work that uses g must be ordered after s.  The geometry never
+// frees that memory.  Throws if g already has tables on this device.
+void geo_place(cbct_geom *g, void *mem, hipStream_t s);
+// Forgets the current device's tables placed by geo_place (no free).
+void geo_unplace(cbct_geom *g);
+
+// ---- solver (piccs.hip) ----
+void check_solve_params(const piccs_params *p);
+// Enqueues a whole solve on s without host synchronisation; copies the scalar
+// block (solve_scalar_count doubles) and the residual history to the host
+// pointers, when non-null, at the end of the stream's work.
+void solve_enqueue(cbct_geom *g, const float *b, const float *xp, float *x,
+                   const piccs_params *p, void *workspace, size_t ws_bytes, hipStream_t s,
+                   double *sc_host, double *hist_host);
+int solve_scalar_count();
+void report_from_scalars(const double *sc, piccs_report *rep);
 
 // ---- projector launchers (proj.hip) ----
 // Forward epilogue modes.

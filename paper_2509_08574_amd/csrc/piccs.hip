@@ -375,7 +375,7 @@ static Workspace carve(const cbct_geom *g, const GeoK &G, const piccs_params *p,
     return W;
 }
 
-static void check_params(const piccs_params *p) {
+void check_solve_params(const piccs_params *p) {
     CBCT_REQUIRE(p != nullptr, "null params");
     CBCT_REQUIRE(std::isfinite(p->alpha) && p->alpha >= 0 && std::isfinite(p->lambda) &&
                      p->lambda >= 0 && std::isfinite(p->tau) && p->tau >= 0,
@@ -386,6 +386,112 @@ static void check_params(const piccs_params *p) {
                      p->precision == CBCT_PREC_MIXED_F16,
                  "unknown precision");
     CBCT_REQUIRE(p->reorth == 0, "reorthogonalisation is not available in this build");
+}
+
+// Enqueues one whole IRN-PICCS solve on stream s (no host synchronisation).
+// When sc_host / hist_host are non-null, the device scalar block and the
+// residual history are copied there, stream-ordered, at the end.
+void solve_enqueue(cbct_geom *g, const float *b, const float *xp, float *x,
+                   const piccs_params *p, void *workspace, size_t ws_bytes, hipStream_t s,
+                   double *sc_host, double *hist_host) {
+    CBCT_REQUIRE(((uintptr_t)workspace & 255) == 0, "workspace must be 256-byte aligned");
+    GeoK G = geo_for_device(g);
+    Workspace W = carve(g, G, p, (char *)workspace);
+    CBCT_REQUIRE(ws_bytes >= W.bytes, "workspace too small (see piccs_workspace_bytes)");
+
+    const int64_t ncz = g->n_col() * G.Z;
+    const unsigned nvb = (unsigned)vox_blocks(G);
+    const float alpha = (float)p->alpha, lam = (float)p->lambda;
+    const float tau2 = (float)(p->tau * p->tau);
+
+    // padded column copies of the inputs (pads and guards zero)
+    launch_fill(W.x - kGuard, W.cstride * 13, 0.0f, s);
+    const int dt = p->precision == CBCT_PREC_MIXED_BF16   ? CBCT_BF16
+                   : p->precision == CBCT_PREC_MIXED_F16 ? CBCT_F16
+                                                          : CBCT_F32;
+    if (dt != CBCT_F32) launch_fill((float *)W.V16buf, (int64_t)(W.v16_bytes / 4), 0.0f, s);
+    const double nvox = (double)g->n_vox();
+    auto xw = [&]() {
+        if (dt == CBCT_BF16)
+            hipLaunchKernelGGL(k_xw<CBCT_BF16>, dim3(4096), dim3(256), 0, s, W.x, W.w, W.V,
+                               W.V16, ncz, W.sc, W.fl);
+        else if (dt == CBCT_F16)
+            hipLaunchKernelGGL(k_xw<CBCT_F16>, dim3(4096), dim3(256), 0, s, W.x, W.w, W.V,
+                               W.V16, ncz, W.sc, W.fl);
+        else
+            hipLaunchKernelGGL(k_xw<CBCT_F32>, dim3(4096), dim3(256), 0, s, W.x, W.w, W.V,
+                               (unsigned short *)nullptr, ncz, W.sc, W.fl);
+    };
+    vol_to_cols(G, x, W.x, s);
+    vol_to_cols(G, xp, W.xp, s);
+    proj_to_cols(G, b, W.bhat, true, s);  // b-hat = L * b
+    hipLaunchKernelGGL(k_solve_begin, dim3(1), dim3(1), 0, s, W.sc, W.fl, W.hist,
+                       p->n_outer * p->n_inner);
+
+    FwdArgs fa{};
+    fa.out = W.uhat;
+    fa.uin = nullptr;
+    fa.partial = W.pf;
+    fa.brk = W.fl;
+    int it_global = 0;
+    for (int ko = 0; ko < p->n_outer; ++ko) {
+        hipLaunchKernelGGL(k_outer_begin, dim3(1), dim3(1), 0, s, W.sc, W.fl);
+        hipLaunchKernelGGL(k_weights, dim3(nvb), dim3(256), 0, s, G, W.x, W.xp, tau2, W.W1,
+                           W.W2);
+        // beta_1 u_1 = b~ - A~ x_{k-1}
+        fa.vol = W.x; fa.uin = W.bhat; fa.s1 = W.sc + SC_M1; fa.s2 = W.sc + SC_P1;
+        launch_forward(G, FWD_SOLVER, fa, s);
+        hipLaunchKernelGGL(k_regF<true>, dim3(nvb), dim3(256), 0, s, G, W.x, W.xp, W.W1,
+                           W.W2, W.u1, W.u2, W.cstride, alpha, lam, W.sc + SC_M1,
+                           W.sc + SC_ZERO, W.pr, W.fl);
+        hipLaunchKernelGGL(k_red<RED_INIT_BETA>, dim3(1), dim3(1024), 0, s, W.pf, W.nf,
+                           W.pr, W.nr, W.sc, W.fl, W.hist, 0, dt, nvox);
+        // alpha_1 v_1 = A~^T u_1
+        launch_back(G, W.uhat, W.t, W.fl, s);
+        hipLaunchKernelGGL(k_regA, dim3(nvb), dim3(256), 0, s, G, W.t, W.W1, W.W2, W.u1,
+                           W.u2, W.cstride, alpha, lam, W.V, W.sc + SC_BACK_S1,
+                           W.sc + SC_BACK_S2, W.pa, W.fl);
+        hipLaunchKernelGGL(k_red<RED_INIT_ALPHA>, dim3(1), dim3(1024), 0, s, W.pa, W.nr,
+                           (const double *)nullptr, (int64_t)0, W.sc, W.fl, W.hist, 0, dt,
+                           nvox);
+        xw();
+        for (int ki = 0; ki < p->n_inner; ++ki, ++it_global) {
+            fa.vol = dt == CBCT_F32 ? (const void *)W.V : (const void *)W.V16;
+            fa.uin = W.uhat; fa.s1 = W.sc + SC_FWD_S1; fa.s2 = W.sc + SC_FWD_S2;
+            launch_forward(G, FWD_SOLVER, fa, s, dt);
+            hipLaunchKernelGGL(k_regF<false>, dim3(nvb), dim3(256), 0, s, G, W.V,
+                               (const float *)nullptr, W.W1, W.W2, W.u1, W.u2, W.cstride,
+                               alpha, lam, W.sc + SC_REG_S1, W.sc + SC_REG_S2, W.pr, W.fl);
+            hipLaunchKernelGGL(k_red<RED_BETA>, dim3(1), dim3(1024), 0, s, W.pf, W.nf,
+                               W.pr, W.nr, W.sc, W.fl, W.hist, it_global, dt, nvox);
+            launch_back(G, W.uhat, W.t, W.fl, s);
+            hipLaunchKernelGGL(k_regA, dim3(nvb), dim3(256), 0, s, G, W.t, W.W1, W.W2, W.u1,
+                               W.u2, W.cstride, alpha, lam, W.V, W.sc + SC_BACK_S1,
+                               W.sc + SC_BACK_S2, W.pa, W.fl);
+            hipLaunchKernelGGL(k_red<RED_ALPHA>, dim3(1), dim3(1024), 0, s, W.pa, W.nr,
+                               (const double *)nullptr, (int64_t)0, W.sc, W.fl, W.hist,
+                               it_global, dt, nvox);
+            xw();
+        }
+    }
+    hipLaunchKernelGGL(k_solve_end, dim3(1), dim3(1), 0, s, W.sc, W.fl);
+    CBCT_HIP(hipGetLastError());
+    cols_to_vol(G, W.x, x, s);
+
+    if (sc_host)
+        CBCT_HIP(hipMemcpyAsync(sc_host, W.sc, sizeof(double) * SC_COUNT, hipMemcpyDeviceToHost,
+                                s));
+    if (hist_host)
+        CBCT_HIP(hipMemcpyAsync(hist_host, W.hist, sizeof(double) * p->n_outer * p->n_inner,
+                                hipMemcpyDeviceToHost, s));
+}
+
+int solve_scalar_count() { return SC_COUNT; }
+
+void report_from_scalars(const double *sc, piccs_report *rep) {
+    rep->inner_done = (int32_t)sc[SC_INNER_DONE];
+    rep->outer_done = (int32_t)sc[SC_OUTER_DONE];
+    rep->breakdown = (int32_t)sc[SC_NBRK];
 }
 
 }  // namespace cbct
@@ -445,7 +551,7 @@ int piccs_workspace_bytes(const cbct_geom *gc, const piccs_params *p, size_t *by
     try {
         clear_last_error();
         CBCT_REQUIRE(gc && bytes, "null argument");
-        check_params(p);
+        check_solve_params(p);
         cbct_geom *g = const_cast<cbct_geom *>(gc);
         GeoK G{};
         G.nx = g->d.nx; G.ny = g->d.ny; G.nz = g->d.nz; G.nu = g->d.nu; G.nv = g->d.nv;
@@ -463,108 +569,15 @@ int piccs_krylov_solve(const cbct_geom *gc, const float *b, const float *xp, flo
     try {
         clear_last_error();
         CBCT_REQUIRE(gc && b && xp && x && workspace, "null argument");
-        check_params(p);
-        CBCT_REQUIRE(((uintptr_t)workspace & 255) == 0, "workspace must be 256-byte aligned");
-        cbct_geom *g = const_cast<cbct_geom *>(gc);
+        check_solve_params(p);
         hipStream_t s = (hipStream_t)hip_stream;
-        GeoK G = geo_for_device(g);
-        Workspace W = carve(g, G, p, (char *)workspace);
-        CBCT_REQUIRE(ws_bytes >= W.bytes, "workspace too small (see piccs_workspace_bytes)");
-
-        const int64_t pf = g->pad_floats();
-        const int64_t ncz = g->n_col() * G.Z;
-        const unsigned nvb = (unsigned)vox_blocks(G);
-        const float alpha = (float)p->alpha, lam = (float)p->lambda;
-        const float tau2 = (float)(p->tau * p->tau);
-
-        // padded column copies of the inputs (pads and guards zero)
-        launch_fill(W.x - kGuard, W.cstride * 13, 0.0f, s);
-        const int dt = p->precision == CBCT_PREC_MIXED_BF16   ? CBCT_BF16
-                       : p->precision == CBCT_PREC_MIXED_F16 ? CBCT_F16
-                                                              : CBCT_F32;
-        if (dt != CBCT_F32) launch_fill((float *)W.V16buf, (int64_t)(W.v16_bytes / 4), 0.0f, s);
-        const double nvox = (double)g->n_vox();
-        auto xw = [&]() {
-            if (dt == CBCT_BF16)
-                hipLaunchKernelGGL(k_xw<CBCT_BF16>, dim3(4096), dim3(256), 0, s, W.x, W.w, W.V,
-                                   W.V16, ncz, W.sc, W.fl);
-            else if (dt == CBCT_F16)
-                hipLaunchKernelGGL(k_xw<CBCT_F16>, dim3(4096), dim3(256), 0, s, W.x, W.w, W.V,
-                                   W.V16, ncz, W.sc, W.fl);
-            else
-                hipLaunchKernelGGL(k_xw<CBCT_F32>, dim3(4096), dim3(256), 0, s, W.x, W.w, W.V,
-                                   (unsigned short *)nullptr, ncz, W.sc, W.fl);
-        };
-        vol_to_cols(G, x, W.x, s);
-        vol_to_cols(G, xp, W.xp, s);
-        proj_to_cols(G, b, W.bhat, true, s);  // b-hat = L * b
-        hipLaunchKernelGGL(k_solve_begin, dim3(1), dim3(1), 0, s, W.sc, W.fl, W.hist,
-                           p->n_outer * p->n_inner);
-
-        FwdArgs fa{};
-        fa.out = W.uhat;
-        fa.uin = nullptr;
-        fa.partial = W.pf;
-        fa.brk = W.fl;
-        int it_global = 0;
-        for (int ko = 0; ko < p->n_outer; ++ko) {
-            hipLaunchKernelGGL(k_outer_begin, dim3(1), dim3(1), 0, s, W.sc, W.fl);
-            hipLaunchKernelGGL(k_weights, dim3(nvb), dim3(256), 0, s, G, W.x, W.xp, tau2, W.W1,
-                               W.W2);
-            // beta_1 u_1 = b~ - A~ x_{k-1}
-            fa.vol = W.x; fa.uin = W.bhat; fa.s1 = W.sc + SC_M1; fa.s2 = W.sc + SC_P1;
-            launch_forward(G, FWD_SOLVER, fa, s);
-            hipLaunchKernelGGL(k_regF<true>, dim3(nvb), dim3(256), 0, s, G, W.x, W.xp, W.W1,
-                               W.W2, W.u1, W.u2, W.cstride, alpha, lam, W.sc + SC_M1,
-                               W.sc + SC_ZERO, W.pr, W.fl);
-            hipLaunchKernelGGL(k_red<RED_INIT_BETA>, dim3(1), dim3(1024), 0, s, W.pf, W.nf,
-                               W.pr, W.nr, W.sc, W.fl, W.hist, 0, dt, nvox);
-            // alpha_1 v_1 = A~^T u_1
-            launch_back(G, W.uhat, W.t, W.fl, s);
-            hipLaunchKernelGGL(k_regA, dim3(nvb), dim3(256), 0, s, G, W.t, W.W1, W.W2, W.u1,
-                               W.u2, W.cstride, alpha, lam, W.V, W.sc + SC_BACK_S1,
-                               W.sc + SC_BACK_S2, W.pa, W.fl);
-            hipLaunchKernelGGL(k_red<RED_INIT_ALPHA>, dim3(1), dim3(1024), 0, s, W.pa, W.nr,
-                               (const double *)nullptr, (int64_t)0, W.sc, W.fl, W.hist, 0, dt,
-                               nvox);
-            xw();
-            for (int ki = 0; ki < p->n_inner; ++ki, ++it_global) {
-                fa.vol = dt == CBCT_F32 ? (const void *)W.V : (const void *)W.V16;
-                fa.uin = W.uhat; fa.s1 = W.sc + SC_FWD_S1; fa.s2 = W.sc + SC_FWD_S2;
-                launch_forward(G, FWD_SOLVER, fa, s, dt);
-                hipLaunchKernelGGL(k_regF<false>, dim3(nvb), dim3(256), 0, s, G, W.V,
-                                   (const float *)nullptr, W.W1, W.W2, W.u1, W.u2, W.cstride,
-                                   alpha, lam, W.sc + SC_REG_S1, W.sc + SC_REG_S2, W.pr, W.fl);
-                hipLaunchKernelGGL(k_red<RED_BETA>, dim3(1), dim3(1024), 0, s, W.pf, W.nf,
-                                   W.pr, W.nr, W.sc, W.fl, W.hist, it_global, dt, nvox);
-                launch_back(G, W.uhat, W.t, W.fl, s);
-                hipLaunchKernelGGL(k_regA, dim3(nvb), dim3(256), 0, s, G, W.t, W.W1, W.W2, W.u1,
-                                   W.u2, W.cstride, alpha, lam, W.V, W.sc + SC_BACK_S1,
-                                   W.sc + SC_BACK_S2, W.pa, W.fl);
-                hipLaunchKernelGGL(k_red<RED_ALPHA>, dim3(1), dim3(1024), 0, s, W.pa, W.nr,
-                                   (const double *)nullptr, (int64_t)0, W.sc, W.fl, W.hist,
-                                   it_global, dt, nvox);
-                xw();
-            }
-        }
-        hipLaunchKernelGGL(k_solve_end, dim3(1), dim3(1), 0, s, W.sc, W.fl);
-        CBCT_HIP(hipGetLastError());
-        cols_to_vol(G, W.x, x, s);
-        (void)pf;
-
+        const int nh = p->n_outer * p->n_inner;
+        std::vector<double> sc(SC_COUNT), hist(rep && rep->resid_hist ? (size_t)nh : 0);
+        solve_enqueue(const_cast<cbct_geom *>(gc), b, xp, x, p, workspace, ws_bytes, s,
+                      rep ? sc.data() : nullptr, hist.empty() ? nullptr : hist.data());
         if (rep) {
-            std::vector<double> sc(SC_COUNT);
-            CBCT_HIP(hipMemcpyAsync(sc.data(), W.sc, sizeof(double) * SC_COUNT,
-                                    hipMemcpyDeviceToHost, s));
-            const int nh = p->n_outer * p->n_inner;
-            std::vector<double> hist((size_t)nh);
-            if (rep->resid_hist)
-                CBCT_HIP(hipMemcpyAsync(hist.data(), W.hist, sizeof(double) * nh,
-                                        hipMemcpyDeviceToHost, s));
             CBCT_HIP(hipStreamSynchronize(s));
-            rep->inner_done = (int32_t)sc[SC_INNER_DONE];
-            rep->outer_done = (int32_t)sc[SC_OUTER_DONE];
-            rep->breakdown = (int32_t)sc[SC_NBRK];
+            report_from_scalars(sc.data(), rep);
             if (rep->resid_hist)
                 for (int q = 0; q < nh; ++q) rep->resid_hist[q] = hist[(size_t)q];
         }

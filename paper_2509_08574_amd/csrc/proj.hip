@@ -72,16 +72,11 @@ k_segtab(GeoK G, int2 *__restrict__ seghdr, int2 *__restrict__ seg) {
     seghdr[r] = make_int2(__float_as_int(a_in), n);
 }
 
-void build_segment_tables(const GeoK &G, int2 *seghdr, int2 *seg) {
-    hipStream_t s;
-    CBCT_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+void launch_segment_tables(const GeoK &G, int2 *seghdr, int2 *seg, hipStream_t s) {
     const int nr = G.nviews * G.nu;
     hipLaunchKernelGGL(k_segtab, dim3((unsigned)((nr + 255) / 256)), dim3(256), 0, s, G, seghdr,
                        seg);
-    hipError_t e = hipGetLastError();
-    if (e == hipSuccess) e = hipStreamSynchronize(s);
-    (void)hipStreamDestroy(s);
-    CBCT_HIP(e);
+    CBCT_HIP(hipGetLastError());
 }
 
 // ---------------------------------------------------------------- forward

@@ -187,3 +187,44 @@ def c2_case(seed: int = 2):
     # to a peak of 1 (water) so that line integrals stay at mu * p = O(1-5).
     scale = 1.0 / base.max()
     return base * scale, cur * scale
+
+
+# --------------------------------------------------------------------------
+# Serving stream: repeated scans of several patients, each the patient's prior
+# plus a needle moved along its own axis.
+
+SERVING_SIZES = (128, 256, 384)
+SERVING_PARAMS = dict(alpha=1.0, lam=1.0, tau=0.1, n_outer=3, n_inner=10, I0=5e4)
+
+
+def serving_patient(i: int, sizes=SERVING_SIZES):
+    """Patient i (seed 400 + i): (n, prior volume, needle (centre, axis)).
+
+    The prior is a 30-ellipsoid object (semi-axes U[4, 24] * n/64 voxels),
+    scaled to a peak of 1, with a needle (radius 1 voxel, length 40 voxels,
+    value 2.0) set into it at a seeded position and direction.
+    """
+    rng = np.random.default_rng(400 + i)
+    n = int(sizes[rng.integers(len(sizes))])
+    base, _ = ellipsoid_phantom((n, n, n), 30, (4.0 * n / 64, 24.0 * n / 64), 400 + i)
+    base *= 1.0 / base.max()
+    centre = np.array([rng.uniform(0.35 * n, 0.65 * n) for _ in range(3)])
+    axis = random_unit(rng)
+    prior = base.copy()
+    add_cylinder(prior, centre, axis, 1.0, 40.0, 2.0)
+    return n, prior, (base, centre, axis)
+
+
+def serving_current(patient_state, shift_voxels: float):
+    """The patient's object with the needle moved by shift_voxels along its axis."""
+    base, centre, axis = patient_state
+    cur = base.copy()
+    add_cylinder(cur, centre + shift_voxels * axis, axis, 1.0, 40.0, 2.0)
+    return cur
+
+
+def serving_request_draw(i: int, n_patients: int):
+    """Request i (seed 4000 + i): (patient, number of views, needle shift in voxels)."""
+    rng = np.random.default_rng(4000 + i)
+    return (int(rng.integers(n_patients)), int(rng.integers(30, 121)),
+            float(rng.uniform(2.0, 5.0)))

@@ -76,3 +76,48 @@ def test_null_arguments_are_rejected(lib):
     assert so.cbct_forward(g.handle, None, 0, 1.0, None, None) == lib.ERR_INVALID
     assert "null" in lib.last_error()
     assert so.cbct_geom_sizes(None, None, None) == lib.ERR_INVALID
+
+
+def _al(n):
+    return (n + 255) // 256 * 256
+
+
+def test_server_footprint_is_the_sum_of_its_buffers(lib):
+    p = lib.SolveParams(1.0, 1.0, 0.1, 3, 10, precision=lib.PREC_MIXED_BF16)
+    g = lib.Geometry(**C1)
+    f = lib.server_footprint(C1, p)
+    M, N = 64 ** 3, 48 * 96 * 96
+    assert f["request"] == _al(4 * N) + _al(4 * M) + _al(lib.workspace_bytes(g, p))
+    assert f["resident"] == 2 * _al(4 * M)
+    # per (view, u): two float4/float2 coefficient entries, a segment header
+    # and up to nx + ny - 1 + 4 segments of 8 bytes; per row / column / view a
+    # few floats; each part padded to 256 bytes
+    rays = 48 * 96
+    core = rays * (16 + 8 + 8 + 8 * (64 + 64 - 1 + 4)) + 96 * (16 + 4) + 96 * 4 + 48 * 8
+    assert core <= f["tables"] <= core + 8 * 256
+    with pytest.raises(lib.CbctError) as ei:
+        lib.server_footprint(dict(C1, nx=0), p)
+    assert ei.value.code == lib.ERR_INVALID
+
+
+def test_server_argument_checks(lib):
+    so = lib._lib
+    assert so.cbct_server_submit(None, None, None) == lib.ERR_INVALID
+    assert so.cbct_server_poll(None, 1, None, None) == lib.ERR_INVALID
+    assert so.cbct_server_stats_get(None, None) == lib.ERR_INVALID
+    assert so.cbct_server_add_prior(None, 0, None, None) == lib.ERR_INVALID
+    assert so.cbct_server_destroy(None) == lib.OK
+    cfg = lib.ServerConfig(1 << 20, 0, 0, 0)
+    h = ctypes.c_void_p()
+    assert so.cbct_server_create(ctypes.byref(cfg), ctypes.byref(h)) == lib.ERR_INVALID
+    assert "max_slots" in lib.last_error()
+
+
+def test_server_create_without_a_device_fails_cleanly(lib):
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a device is present")
+    cfg = lib.ServerConfig(1 << 20, 2, 0, 0)
+    h = ctypes.c_void_p()
+    rc = lib._lib.cbct_server_create(ctypes.byref(cfg), ctypes.byref(h))
+    assert rc in (lib.ERR_INVALID, lib.ERR_DEVICE) and not h.value

@@ -1,0 +1,237 @@
+"""GPU tests of the reconstruction server (continuous batching of IRN-PICCS).
+
+Every served result is checked against a direct piccs_krylov_solve of the
+same inputs (bit-for-bit: same kernels, fixed reduction order, nothing in a
+solve depends on what else runs), and one against the FP64 oracle.  The
+alone-vs-mix test serves each patient's chain alone on a fresh server and
+again interleaved with the other patients' requests on one server with
+several slots, and requires identical results.
+"""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+SOLVE_TOL = 1e-4
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2509_08574_amd import cbct
+    return cbct
+
+
+def geom(n, views, angles=None):
+    g = dict(nx=n, ny=n, nz=n, vx=64.0 / n, vy=64.0 / n, vz=64.0 / n, nu=3 * n // 2,
+             nv=3 * n // 2, du=96.0 / n, dv=96.0 / n, dso=1000.0, dsd=1536.0, n_views=views)
+    if angles is not None:
+        g["angles"] = list(angles)
+    return g
+
+
+def patient(orc, pid, n):
+    """Prior and a needle to move, on the oracle's side of the fence."""
+    from paper_2509_08574_amd import synth
+    prior, _ = synth.ellipsoid_phantom((n, n, n), 8, (3.0 * n / 48, 16.0 * n / 48), 50 + pid)
+    prior = prior.astype(np.float32)
+    return prior
+
+
+def request_b(orc, g, prior, shift, seed):
+    from paper_2509_08574_amd import synth
+    n = g["nx"]
+    cur = prior.astype(np.float64).copy()
+    rng = np.random.default_rng(seed)
+    c = np.array([rng.uniform(0.4 * n, 0.6 * n) for _ in range(3)])
+    axis = synth.random_unit(rng)
+    synth.add_cylinder(cur, c + shift * axis, axis, 1.0, 0.5 * n, 2.0)
+    p = orc.forward(orc.Geometry.from_dict(g), cur)
+    return synth.noisy_line_integrals(p, 1e5, seed).astype(np.float32)
+
+
+PARAMS = dict(alpha=1.0, lam=1.0, tau=0.1, n_outer=2, n_inner=4)
+
+
+def direct(lib, g, b, xp, x0, p):
+    import torch
+    gg = lib.Geometry.from_dict(g)
+    x = torch.from_numpy(np.ascontiguousarray(x0, dtype=np.float32)).cuda()
+    x, rep = lib.solve(gg, torch.from_numpy(b).cuda(), torch.from_numpy(xp).cuda(), x, p)
+    out = x.cpu().numpy()
+    gg.close()
+    return out, rep
+
+
+def serve_chain(srv, reqs, out_shape):
+    """Submit all requests, then collect; returns list of (x, info)."""
+    tickets = [srv.submit(pid, g, b, p, x0) for (pid, g, b, p, x0) in reqs]
+    res = []
+    for t, (pid, g, b, p, x0) in zip(tickets, reqs):
+        out = np.empty(out_shape[pid], dtype=np.float32)
+        rc, x, info = srv.wait(t, out, hist_len=p.n_outer * p.n_inner)
+        assert rc == 0, info["error"]
+        res.append((x, info))
+    return res
+
+
+def test_served_request_equals_direct_solve_and_oracle(orc, lib):
+    g = geom(48, 36)
+    xp = patient(orc, 0, 48)
+    b = request_b(orc, g, xp, 3.0, 11)
+    p = lib.SolveParams(**PARAMS)
+    with lib.Server(hbm_budget_bytes=1 << 30, max_slots=2) as srv:
+        srv.add_prior(0, g, xp)
+        t = srv.submit(0, g, b, p, lib.X0_PRIOR)
+        rc, x, info = srv.wait(t, np.empty(xp.shape, np.float32), hist_len=8)
+        assert rc == 0
+        assert info["t_submit"] <= info["t_admit"] <= info["t_done"]
+        assert info["inner_done"] == 8 and info["outer_done"] == 2
+        xd, rep = direct(lib, g, b, xp, xp, p)
+        assert np.array_equal(x, xd)
+        assert info["phibar"] == rep["phibar"]
+        ref = orc.irn_piccs(orc.Geometry.from_dict(g), b.astype(np.float64),
+                            xp.astype(np.float64), xp.astype(np.float64), **PARAMS)
+        assert np.linalg.norm(x - ref.x) / np.linalg.norm(ref.x) <= SOLVE_TOL
+        with pytest.raises(lib.CbctError):
+            srv.poll(t)                       # collected once
+
+
+def test_warm_start_from_previous_reconstruction(orc, lib):
+    g1, g2 = geom(40, 30), geom(40, 45)
+    xp = patient(orc, 1, 40)
+    b1 = request_b(orc, g1, xp, 2.0, 21)
+    b2 = request_b(orc, g2, xp, 4.0, 22)
+    p = lib.SolveParams(**PARAMS)
+    with lib.Server(hbm_budget_bytes=1 << 30, max_slots=3) as srv:
+        srv.add_prior(1, g1, xp)
+        (x1, _), (x2, _) = serve_chain(srv, [(1, g1, b1, p, lib.X0_PREVIOUS),
+                                             (1, g2, b2, p, lib.X0_PREVIOUS)],
+                                       {1: xp.shape})
+    d1, _ = direct(lib, g1, b1, xp, xp, p)
+    d2, _ = direct(lib, g2, b2, xp, d1, p)          # starts from the first result
+    assert np.array_equal(x1, d1)
+    assert np.array_equal(x2, d2)
+
+
+def _mixed_workload(orc, lib):
+    """Three patients of two volume sizes, two requests each, mixed view counts
+    and precisions."""
+    specs = {0: 48, 1: 32, 2: 48}
+    priors = {pid: patient(orc, pid, n) for pid, n in specs.items()}
+    reqs = []
+    views = {0: (30, 41), 1: (25, 60), 2: (41, 33)}
+    prec = {0: lib.PREC_FP32, 1: lib.PREC_MIXED_BF16, 2: lib.PREC_MIXED_F16}
+    for k in range(2):
+        for pid, n in specs.items():
+            g = geom(n, views[pid][k])
+            b = request_b(orc, g, priors[pid], 2.0 + k, 100 * pid + k)
+            p = lib.SolveParams(**PARAMS, precision=prec[pid])
+            reqs.append((pid, g, b, p, lib.X0_PREVIOUS))
+    return specs, priors, reqs
+
+
+def test_alone_vs_mix(orc, lib):
+    """Each result is the same alone and served in the mix (exactly)."""
+    specs, priors, reqs = _mixed_workload(orc, lib)
+    shapes = {pid: priors[pid].shape for pid in specs}
+    alone = {}
+    for pid in specs:
+        with lib.Server(hbm_budget_bytes=1 << 30, max_slots=1) as srv:
+            srv.add_prior(pid, geom(specs[pid], 30), priors[pid])
+            mine = [r for r in reqs if r[0] == pid]
+            for r, (x, _) in zip(mine, serve_chain(srv, mine, shapes)):
+                alone[id(r)] = x
+    with lib.Server(hbm_budget_bytes=2 << 30, max_slots=4) as srv:
+        for pid in specs:
+            srv.add_prior(pid, geom(specs[pid], 30), priors[pid])
+        mixed = serve_chain(srv, reqs, shapes)
+        st = srv.stats()
+    for r, (x, info) in zip(reqs, mixed):
+        assert np.array_equal(x, alone[id(r)]), f"patient {r[0]} differs alone vs mix"
+    assert st["completed"] == len(reqs) and st["failed"] == 0
+    assert st["peak_in_flight"] >= 2            # requests really overlapped
+    assert st["peak_used"] <= st["capacity"]
+
+
+def test_small_budget_runs_one_at_a_time(orc, lib):
+    """A budget with room for one request (and half of one geometry's tables
+    besides) serialises the stream and evicts idle tables, with the same
+    results as a roomy budget."""
+    n = 40
+    priors = {pid: patient(orc, pid, n) for pid in (0, 1, 2)}
+    p = lib.SolveParams(**PARAMS)
+    reqs = []
+    for k, pid in enumerate((0, 1, 2, 0, 1, 2)):
+        g = geom(n, 30 + k)                      # six distinct geometries
+        reqs.append((pid, g, request_b(orc, g, priors[pid], 2.0 + k, 300 + k), p,
+                     lib.X0_PREVIOUS))
+    shapes = {pid: priors[pid].shape for pid in priors}
+    fps = [lib.server_footprint(r[1], p) for r in reqs]
+    budget = (3 * fps[0]["resident"] + max(f["request"] + f["tables"] for f in fps)
+              + min(f["tables"] for f in fps) // 2)
+    with lib.Server(hbm_budget_bytes=budget, max_slots=4) as srv:
+        for pid in priors:
+            srv.add_prior(pid, geom(n, 30), priors[pid])
+        served = serve_chain(srv, reqs, shapes)
+        st = srv.stats()
+    assert st["peak_in_flight"] == 1 and st["completed"] == len(reqs)
+    assert st["peak_used"] <= st["capacity"]
+    assert st["geom_evictions"] >= len(reqs) - 1   # each new geometry needed the room
+    with lib.Server(hbm_budget_bytes=1 << 30, max_slots=4) as srv:
+        for pid in priors:
+            srv.add_prior(pid, geom(n, 30), priors[pid])
+        roomy = serve_chain(srv, reqs, shapes)
+        assert srv.stats()["peak_in_flight"] >= 2
+    for (a, _), (b_, _) in zip(served, roomy):
+        assert np.array_equal(a, b_)
+
+
+def test_refusals(orc, lib):
+    g = geom(32, 20)
+    xp = patient(orc, 3, 32)
+    b = np.zeros((20, 48, 48), np.float32)
+    p = lib.SolveParams(**PARAMS)
+    fp = lib.server_footprint(g, p)
+    with lib.Server(hbm_budget_bytes=fp["resident"] + fp["request"] // 2, max_slots=2) as srv:
+        srv.add_prior(3, g, xp)
+        with pytest.raises(lib.CbctError) as e:
+            srv.submit(3, g, b, p)
+        assert e.value.code == lib.ERR_OOM
+        with pytest.raises(lib.CbctError) as e:
+            srv.submit(4, g, b, p)
+        assert e.value.code == lib.ERR_NOT_FOUND
+        with pytest.raises(lib.CbctError) as e:
+            srv.submit(3, geom(40, 20), np.zeros((20, 60, 60), np.float32), p)
+        assert e.value.code == lib.ERR_INVALID        # not the patient's volume
+        with pytest.raises(lib.CbctError) as e:
+            srv.add_prior(3, g, xp)
+        assert e.value.code == lib.ERR_INVALID        # registered already
+        with pytest.raises(lib.CbctError) as e:
+            srv.add_prior(5, geom(64, 20), np.zeros(64 ** 3, np.float32))
+        assert e.value.code == lib.ERR_OOM
+
+
+def test_queue_limit(orc, lib):
+    g = geom(32, 20)
+    xp = patient(orc, 6, 32)
+    b = request_b(orc, g, xp, 2.0, 61)
+    p = lib.SolveParams(**PARAMS)
+    with lib.Server(hbm_budget_bytes=1 << 30, max_slots=1, max_queue=2) as srv:
+        srv.add_prior(6, g, xp)
+        # one slot, two waiting: submitting faster than a solve finishes
+        # must hit the limit
+        got, busy = [], False
+        for _ in range(50):
+            try:
+                got.append(srv.submit(6, g, b, p, lib.X0_PRIOR))
+            except lib.CbctError as e:
+                assert e.code == lib.ERR_BUSY
+                busy = True
+                break
+        assert busy and len(got) >= 3
+        outs = [srv.wait(t, np.empty(xp.shape, np.float32))[1] for t in got]
+    for x in outs[1:]:
+        assert np.array_equal(x, outs[0])            # same request, same result
