@@ -30,6 +30,230 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+PROFILES = os.path.join(ROOT, "profiles")
+# sources that define the projector kernels: a recorded HBM traffic figure is
+# only used while these are byte-identical to what was profiled
+KERNEL_SOURCES = ("paper_2509_08574_amd/csrc/proj.hip", "paper_2509_08574_amd/csrc/chord.h",
+                  "paper_2509_08574_amd/csrc/internal.h")
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def recorded_traffic(kernel, workload):
+    """HBM bytes per launch from the committed rocprofv3 summary of `kernel` on
+    `workload` (FETCH_SIZE + WRITE_SIZE, calibrated), or None if there is none
+    or the kernel sources changed since it was taken."""
+    path = os.path.join(PROFILES, f"{kernel}_{workload}.md")
+    if not os.path.exists(path):
+        return None
+    rec = {}
+    with open(path) as fh:
+        for line in fh:
+            if ":" in line and line.startswith("- `"):
+                k, v = line[3:].split("`", 1)[0], line.split(":", 1)[1].strip().strip("`")
+                rec[k] = v
+    if rec.get("kernel_source_sha256") != kernel_source_hash():
+        return None
+    try:
+        return float(rec["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def projector_roofline(args, cbct, torch, g, xc, ywc, stream):
+    """Event-timed isolated A and A^T (column layout, on `stream`) and the
+    operand-bytes roofline of the slower one."""
+    M, N = g.sizes()
+    V = g.proj_shape[0]
+    yc = torch.empty_like(ywc)
+    xo = torch.empty_like(xc)
+
+    def time_op(fn, reps):
+        fn()
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        ev0.record(stream)
+        for _ in range(reps):
+            fn()
+        ev1.record(stream)
+        ev1.synchronize()
+        return ev0.elapsed_time(ev1) / reps
+
+    t_fwd = time_op(lambda: cbct.forward_cols(g, xc, yc, stream=stream), args.op_reps)
+    t_back = time_op(lambda: cbct.back_cols(g, ywc, xo, stream=stream), args.op_reps)
+    nnz = g.nnz()
+    bytes_fwd = 4.0 * nnz + 4.0 * N
+    bytes_back = 4.0 * nnz + 4.0 * M
+    gvp_fwd = M * V / (t_fwd * 1e-3) / 1e9
+    gvp_back = M * V / (t_back * 1e-3) / 1e9
+    dom = ("k_back", t_back, bytes_back) if t_back >= t_fwd else ("k_fwd", t_fwd, bytes_fwd)
+    achieved = dom[2] / (dom[1] * 1e-3) / 1e9
+    log(f"[bench] A {t_fwd:.3f} ms ({gvp_fwd:.1f} Gvp/s), A^T {t_back:.3f} ms "
+        f"({gvp_back:.1f} Gvp/s), nnz {nnz}")
+    traffic = recorded_traffic(dom[0], args.workload)
+    roofline = {"bound": "hbm", "kernel": dom[0], "achieved": round(achieved, 1),
+                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": traffic, "avg_launch_ms": round(dom[1], 4),
+                "algorithmic_bytes_per_launch": dom[2], "units_per_launch": nnz,
+                "unit_bytes": "4 B per chord + 4 B per output element",
+                "traffic_source": f"profiles/{dom[0]}_{args.workload}.md" if traffic else None}
+    return t_fwd, t_back, nnz, gvp_fwd, gvp_back, roofline
+
+
+def serving_bench(args, cbct, synth, np, torch, dev):
+    """Serving stream: 8 patients with resident priors (volumes 128/256/384^3,
+    detector 2n x 2n, 30..120 views per request, needle moved 2..5 voxels),
+    IRN-PICCS 3x10 in mixed BF16.  Returns a dict for the JSON line.
+
+    Requests come from a seeded pool of distinct scans (projections made on the
+    device before timing).  Three passes: each pool request alone (service
+    time), the whole pool submitted at once (closed-loop capacity), then a
+    Poisson stream at rate rho x capacity.  Latency runs from the scheduled
+    arrival to the moment the result is ready to poll.
+    """
+    sp = synth.SERVING_PARAMS
+    params = cbct.SolveParams(sp["alpha"], sp["lam"], sp["tau"], sp["n_outer"], sp["n_inner"],
+                              precision=cbct.PREC_MIXED_BF16)
+    t_setup = time.time()
+    n_pat = 8
+    from concurrent.futures import ThreadPoolExecutor
+    with ThreadPoolExecutor(8) as ex:
+        pats = list(ex.map(synth.serving_patient, range(n_pat)))
+    log(f"[serve] {n_pat} patients, sizes {[n for n, _, _ in pats]} "
+        f"({time.time() - t_setup:.1f}s)")
+    srv = cbct.Server(hbm_budget_bytes=args.serve_budget_gib << 30, max_slots=args.serve_slots)
+    base_d = {}
+    for i, (n, prior, state) in enumerate(pats):
+        srv.add_prior(i, synth.serving_geometry(n, 30), prior.astype(np.float32))
+        base_d[i] = torch.from_numpy(state[0].astype(np.float32)).to(dev)
+
+    # request pool: (patient, geometry, b)
+    gen = torch.Generator(device=dev)
+    pool = []
+    for i in range(args.serve_pool):
+        pid, nv, shift = synth.serving_request_draw(i, n_pat)
+        n, _, state = pats[pid]
+        gdict = synth.serving_geometry(n, nv)
+        gq = cbct.Geometry.from_dict(gdict)
+        cur = base_d[pid].clone()
+        cur.view(-1)[torch.from_numpy(synth.serving_needle(state, shift)).to(dev)] = 2.0
+        y = cbct.forward(gq, cur)
+        gen.manual_seed(4000 + i)
+        lam = sp["I0"] * torch.exp(-synth.MU_WATER_PER_MM * y.double())
+        counts = torch.clamp(torch.poisson(lam, generator=gen), min=1.0)
+        b = (-torch.log(counts / sp["I0"]) / synth.MU_WATER_PER_MM).float().cpu().numpy()
+        pool.append((pid, gdict, b))
+        gq.close()
+        del cur, y, lam, counts
+    torch.cuda.synchronize()
+    del base_d
+    log(f"[serve] pool of {len(pool)} requests ready ({time.time() - t_setup:.1f}s)")
+    outs = {i: np.empty((n, n, n), np.float32) for i, (n, _, _) in enumerate(pats)}
+
+    def run_one(k):
+        pid, gdict, b = pool[k]
+        t = srv.submit(pid, gdict, b, params)
+        rc, _, info = srv.wait(t, outs[pid], timeout=600)
+        assert rc == 0, info["error"]
+        return info
+
+    # pass 1: alone (also warms geometry tables and pinned buffers)
+    alone = [run_one(k) for k in range(len(pool))]
+    service = [a["t_done"] - a["t_submit"] for a in alone]
+    by_size = {}
+    for (pid, _, _), s_ in zip(pool, service):
+        by_size.setdefault(pats[pid][0], []).append(s_)
+    log(f"[serve] alone: mean service {np.mean(service) * 1e3:.1f} ms; "
+        + ", ".join(f"{n}^3 {np.mean(v) * 1e3:.0f} ms" for n, v in sorted(by_size.items())))
+
+    # pass 2: closed loop, the whole pool at once
+    t = time.perf_counter()
+    tickets = [srv.submit(pid, g_, b, params) for pid, g_, b in pool]
+    for tk, (pid, _, _) in zip(tickets, pool):
+        rc, _, info = srv.wait(tk, outs[pid], timeout=600)
+        assert rc == 0, info["error"]
+    t_closed = time.perf_counter() - t
+    capacity = len(pool) / t_closed
+    log(f"[serve] closed loop: {capacity:.2f} recon/s "
+        f"(serial {len(pool) / sum(service):.2f} recon/s)")
+
+    # pass 3: Poisson arrivals at rho x capacity
+    results = {}
+    for rho in args.serve_rho:
+        rate = rho * capacity
+        rng = np.random.default_rng(499)
+        n_req = args.serve_requests + args.serve_warmup
+        gaps = rng.exponential(1.0 / rate, size=n_req)
+        picks = rng.integers(len(pool), size=n_req)
+        arrivals = np.cumsum(gaps)
+        lat, pending = [], {}
+        st0 = srv.stats()
+        t0 = time.perf_counter()
+        nxt = 0
+        while nxt < n_req or pending:
+            now = time.perf_counter() - t0
+            if nxt < n_req and now >= arrivals[nxt]:
+                pid, g_, b = pool[picks[nxt]]
+                t_sub = time.perf_counter() - t0
+                tk = srv.submit(pid, g_, b, params)
+                pending[tk] = (nxt, pid, arrivals[nxt], t_sub)
+                nxt += 1
+                continue
+            for tk in list(pending):
+                k, pid, arr, t_sub = pending[tk]
+                r = srv.poll(tk, outs[pid])
+                if r is None:
+                    continue
+                rc, _, info = r
+                assert rc == 0, info["error"]
+                del pending[tk]
+                if k >= args.serve_warmup:
+                    # late submission adds to the latency
+                    lat.append(info["t_done"] - info["t_submit"] + (t_sub - arr))
+            time.sleep(2e-4)
+        wall = time.perf_counter() - t0
+        st = srv.stats()
+        lat = np.array(lat)
+        results[f"rho_{rho}"] = {
+            "offered_recon_per_s": round(rate, 3),
+            "achieved_recon_per_s": round(n_req / wall, 3),
+            "requests_measured": int(lat.size),
+            "latency_p50_s": round(float(np.percentile(lat, 50)), 4),
+            "latency_p99_s": round(float(np.percentile(lat, 99)), 4),
+            "latency_mean_s": round(float(lat.mean()), 4),
+            "peak_in_flight": st["peak_in_flight"],
+            "failed": st["failed"] - st0["failed"],
+        }
+        log(f"[serve] rho {rho}: p50 {results[f'rho_{rho}']['latency_p50_s'] * 1e3:.0f} ms, "
+            f"p99 {results[f'rho_{rho}']['latency_p99_s'] * 1e3:.0f} ms, "
+            f"{n_req / wall:.2f} recon/s over {wall:.1f}s")
+    st = srv.stats()
+    srv.close()
+    return {
+        "workload": "8 patients (128/256/384^3, detector 2n x 2n), 30..120 views, "
+                    "IRN-PICCS 3x10 mixed bf16, Poisson arrivals",
+        "slots": args.serve_slots,
+        "hbm_budget_gib": args.serve_budget_gib,
+        "pool_requests": len(pool),
+        "service_alone_mean_s": round(float(np.mean(service)), 4),
+        "service_alone_by_size_s": {str(n): round(float(np.mean(v)), 4)
+                                    for n, v in sorted(by_size.items())},
+        "serial_recon_per_s": round(len(pool) / sum(service), 3),
+        "closed_loop_recon_per_s": round(capacity, 3),
+        "streams": results,
+        "peak_used_gib": round(st["peak_used"] / 2 ** 30, 2),
+        "geom_placements": st["geom_placements"],
+        "geom_evictions": st["geom_evictions"],
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -43,6 +267,19 @@ def main():
     ap.add_argument("--op-reps", type=int, default=10)
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also run one plain device copy of this many MiB (profiler calibration)")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving stream")
+    ap.add_argument("--ops-only", action="store_true",
+                    help="time only the projector pair on random data (profiler passes)")
+    ap.add_argument("--serve-only", action="store_true",
+                    help="run only the serving stream and print its JSON")
+    ap.add_argument("--serve-requests", type=int, default=100,
+                    help="measured requests per arrival rate")
+    ap.add_argument("--serve-warmup", type=int, default=10)
+    ap.add_argument("--serve-rho", type=lambda s: [float(v) for v in s.split(",")],
+                    default=[0.7], help="arrival rates as fractions of capacity, e.g. 0.5,0.7,0.9")
+    ap.add_argument("--serve-pool", type=int, default=24)
+    ap.add_argument("--serve-slots", type=int, default=2)
+    ap.add_argument("--serve-budget-gib", type=int, default=64)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
@@ -57,6 +294,31 @@ def main():
     torch.cuda.set_device(0)
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream()
+    if args.ops_only:
+        # the projector pair alone on random data of the workload's shape
+        # (their cost does not depend on the values); for profiler passes
+        gq = cbct.Geometry.from_dict(synth.geometry(args.workload))
+        if args.calib_copy_mib > 0:
+            n = args.calib_copy_mib * (1 << 20) // 4
+            src = torch.ones(n, dtype=torch.float32, device=dev)
+            dst = torch.empty_like(src)
+            dst.copy_(src)
+            torch.cuda.synchronize()
+            del src, dst
+        vf, voff, pf = cbct.col_sizes(gq)
+        gen = torch.Generator(device=dev)
+        gen.manual_seed(7)
+        xc = torch.rand(vf, generator=gen, device=dev)
+        ywc = torch.rand(pf, generator=gen, device=dev)
+        xc = cbct.vol_to_cols(gq, cbct.cols_to_vol(gq, xc))     # zero pads and guards
+        r = projector_roofline(args, cbct, torch, gq, xc, ywc, stream)
+        print(json.dumps({"A_ms": r[0], "AT_ms": r[1], "nnz": r[2], "roofline": r[5]}),
+              flush=True)
+        return
+    if args.serve_only:
+        print(json.dumps({"serving": serving_bench(args, cbct, synth, np, torch, dev)}),
+              flush=True)
+        return
     wl = args.workload
     gd = synth.geometry(wl)
     sp = synth.SOLVE_PARAMS[wl]
@@ -154,39 +416,10 @@ def main():
     forms["fp32"] = {"s_per_recon": round(ms_per_step / 1e3, 4), "speedup_vs_fp32": 1.0}
 
     # ---------------- isolated projector kernels (HIP events on this stream)
-    vf, voff, pf = cbct.col_sizes(g)
     xc = cbct.vol_to_cols(g, cur_d)
-    yc = torch.empty(pf, dtype=torch.float32, device=dev)
     ywc = cbct.proj_to_cols(g, b_d, weighted=True)
-    xo = torch.empty(vf, dtype=torch.float32, device=dev)
-
-    def time_op(fn, reps):
-        fn()
-        ev0 = torch.cuda.Event(enable_timing=True)
-        ev1 = torch.cuda.Event(enable_timing=True)
-        ev0.record(stream)
-        for _ in range(reps):
-            fn()
-        ev1.record(stream)
-        ev1.synchronize()
-        return ev0.elapsed_time(ev1) / reps
-
-    t_fwd = time_op(lambda: cbct.forward_cols(g, xc, yc), args.op_reps)
-    t_back = time_op(lambda: cbct.back_cols(g, ywc, xo), args.op_reps)
-    nnz = g.nnz()
-    bytes_fwd = 4.0 * nnz + 4.0 * N
-    bytes_back = 4.0 * nnz + 4.0 * M
-    gvp_fwd = M * V / (t_fwd * 1e-3) / 1e9
-    gvp_back = M * V / (t_back * 1e-3) / 1e9
-    dom = ("k_back", t_back, bytes_back) if t_back >= t_fwd else ("k_fwd", t_fwd, bytes_fwd)
-    achieved = dom[2] / (dom[1] * 1e-3) / 1e9
-    log(f"[bench] A {t_fwd:.3f} ms ({gvp_fwd:.1f} Gvp/s), A^T {t_back:.3f} ms "
-        f"({gvp_back:.1f} Gvp/s), nnz {nnz}")
-    roofline = {"bound": "hbm", "kernel": dom[0], "achieved": round(achieved, 1),
-                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": None, "avg_launch_ms": round(dom[1], 4),
-                "algorithmic_bytes_per_launch": dom[2], "units_per_launch": nnz,
-                "unit_bytes": "4 B per chord + 4 B per output element"}
+    t_fwd, t_back, nnz, gvp_fwd, gvp_back, roofline = projector_roofline(
+        args, cbct, torch, g, xc, ywc, stream)
 
     # ---------------- CPU oracle baseline (bounded sample)
     cpu = None
@@ -241,6 +474,10 @@ def main():
                 np.linalg.norm(xg1 - ref1.x) / np.linalg.norm(ref1.x))
         cpu["oracle_c1_solve_s"] = round(t_or1, 2)
 
+    serving = None
+    if not args.no_serve:
+        serving = serving_bench(args, cbct, synth, np, torch, dev)
+
     out = {
         "metric": "Gvoxel-proj/s for A and A^T; s/recon + p99 latency, FP32 vs mixed",
         "value": round(value, 3),
@@ -271,6 +508,7 @@ def main():
             "prior": args.prior,
         },
         "precision_forms": forms,
+        "serving": serving,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

@@ -361,6 +361,14 @@ void launch_forward(const GeoK &G, int mode, const FwdArgs &a, hipStream_t s, in
 // most one z plane per segment, this equals its c0 / c1 bit for bit and is 0 for
 // every cell the forward does not touch: the two kernels apply the same matrix.
 // No atomics; every cell is summed in a fixed order.
+#ifndef CBCT_BACK_TILE_W
+#define CBCT_BACK_TILE_W 16
+#endif
+#ifndef CBCT_BACK_TILE_H
+#define CBCT_BACK_TILE_H 16
+#endif
+constexpr int kBackTileW = CBCT_BACK_TILE_W, kBackTileH = CBCT_BACK_TILE_H;
+
 template <int C>
 __global__ void __launch_bounds__(256)
 k_back(GeoK G, const float *__restrict__ yhat, float *__restrict__ out, const int *brk,
@@ -378,10 +386,18 @@ k_back(GeoK G, const float *__restrict__ yhat, float *__restrict__ out, const in
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int nzs = (G.nz + kspan - 1) / kspan;        // z splits per column
     const int64_t lw = (int64_t)xcd_remap(blockIdx.x, gridDim.x) * 4 + w;
-    const int64_t col = lw / nzs;
+    // columns in kBackTileW x kBackTileH tiles, tiles row-major: the waves
+    // resident on one XCD cover a compact patch of the x-y plane, whose
+    // detector footprint in each view is narrow and stays in that XCD's L2
+    const int64_t cw = lw / nzs;
     const int zs = (int)(lw % nzs);
-    if (col >= (int64_t)G.nx * G.ny) return;
-    const int i = (int)(col % G.nx), j = (int)(col / G.nx);
+    const int ntx = (G.nx + kBackTileW - 1) / kBackTileW;
+    const int64_t tile = cw / (kBackTileW * kBackTileH);
+    const int rt = (int)(cw % (kBackTileW * kBackTileH));
+    const int i = (int)(tile % ntx) * kBackTileW + rt % kBackTileW;
+    const int j = (int)(tile / ntx) * kBackTileH + rt / kBackTileW;
+    if (i >= G.nx || j >= G.ny) return;
+    const int64_t col = (int64_t)j * G.nx + i;
     const int kbase = zs * kspan;
 
     constexpr int QM = 8;
@@ -488,7 +504,9 @@ void launch_back(const GeoK &G, const float *yhat, float *out, const int *brk, h
     const int nq = std::min(8, (G.nz + 63) / 64);
     const int kspan = 64 * nq;
     const int nzs = (G.nz + kspan - 1) / kspan;
-    const int64_t nwaves = (int64_t)G.nx * G.ny * nzs;
+    const int64_t ntiles = (int64_t)((G.nx + kBackTileW - 1) / kBackTileW) *
+                           ((G.ny + kBackTileH - 1) / kBackTileH);
+    const int64_t nwaves = ntiles * kBackTileW * kBackTileH * nzs;
     const int64_t nb = (nwaves + 3) / 4;
     if (nb > 0x7fffffff) throw Error(CBCT_ERR_INVALID, "back grid too large");
     const size_t shm = sizeof(float2) * (size_t)G.nv;

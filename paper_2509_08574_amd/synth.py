@@ -49,38 +49,47 @@ def add_ellipsoid(vol: np.ndarray, centre, semi, R, value, mode="add"):
     hi = [min(n, int(math.ceil(centre[a] + rmax)) + 1) for a, n in enumerate((nx, ny, nz))]
     if any(h <= l for l, h in zip(lo, hi)):
         return
-    zc = (np.arange(lo[2], hi[2]) + 0.5 - centre[2])[:, None, None]
     yc = (np.arange(lo[1], hi[1]) + 0.5 - centre[1])[None, :, None]
     xc = (np.arange(lo[0], hi[0]) + 0.5 - centre[0])[None, None, :]
-    acc = 0.0
-    for m in range(3):  # (R^T p)_m / a_m, summed in squares
-        q = (xc * R[0, m] + yc * R[1, m] + zc * R[2, m]) / semi[m]
-        acc = acc + q * q
-    inside = acc <= 1.0
-    sub = vol[lo[2]:hi[2], lo[1]:hi[1], lo[0]:hi[0]]
-    if mode == "add":
-        sub[inside] += value
-    else:
-        sub[inside] = value
+    # z slabs of a few planes keep the temporaries in cache (same arithmetic)
+    for z0 in range(lo[2], hi[2], 8):
+        z1 = min(z0 + 8, hi[2])
+        zc = (np.arange(z0, z1) + 0.5 - centre[2])[:, None, None]
+        acc = 0.0
+        for m in range(3):  # (R^T p)_m / a_m, summed in squares
+            q = (xc * R[0, m] + yc * R[1, m] + zc * R[2, m]) / semi[m]
+            acc = acc + q * q
+        inside = acc <= 1.0
+        sub = vol[z0:z1, lo[1]:hi[1], lo[0]:hi[0]]
+        if mode == "add":
+            sub[inside] += value
+        else:
+            sub[inside] = value
 
 
-def add_cylinder(vol: np.ndarray, centre, axis, radius, length, value):
-    """Set the voxels whose centres lie in a finite cylinder to ``value`` (voxel units)."""
-    nz, ny, nx = vol.shape
+def cylinder_indices(shape, centre, axis, radius, length):
+    """Flat indices (into a [z][y][x] array of `shape`) of the voxels whose
+    centres lie in a finite cylinder (voxel units, (x, y, z))."""
+    nz, ny, nx = shape
     axis = np.asarray(axis, dtype=np.float64)
     axis = axis / np.linalg.norm(axis)
     ext = length / 2.0 + radius + 1
     lo = [max(0, int(math.floor(centre[a] - ext))) for a in range(3)]
     hi = [min(n, int(math.ceil(centre[a] + ext)) + 1) for a, n in enumerate((nx, ny, nz))]
     if any(h <= l for l, h in zip(lo, hi)):
-        return
+        return np.zeros(0, dtype=np.int64)
     zc = (np.arange(lo[2], hi[2]) + 0.5 - centre[2])[:, None, None]
     yc = (np.arange(lo[1], hi[1]) + 0.5 - centre[1])[None, :, None]
     xc = (np.arange(lo[0], hi[0]) + 0.5 - centre[0])[None, None, :]
     t = xc * axis[0] + yc * axis[1] + zc * axis[2]
     r2 = xc * xc + yc * yc + zc * zc - t * t
-    inside = (np.abs(t) <= length / 2.0) & (r2 <= radius * radius)
-    vol[lo[2]:hi[2], lo[1]:hi[1], lo[0]:hi[0]][inside] = value
+    kz, jy, ix = np.nonzero((np.abs(t) <= length / 2.0) & (r2 <= radius * radius))
+    return ((kz + lo[2]) * ny + (jy + lo[1])) * nx + (ix + lo[0])
+
+
+def add_cylinder(vol: np.ndarray, centre, axis, radius, length, value):
+    """Set the voxels whose centres lie in a finite cylinder to ``value`` (voxel units)."""
+    vol.reshape(-1)[cylinder_indices(vol.shape, centre, axis, radius, length)] = value
 
 
 def ellipsoid_phantom(shape, n_ell, semi_range, seed, dens_range=(0.1, 1.0)):
@@ -215,11 +224,17 @@ def serving_patient(i: int, sizes=SERVING_SIZES):
     return n, prior, (base, centre, axis)
 
 
+def serving_needle(patient_state, shift_voxels: float):
+    """Flat voxel indices of the needle moved by shift_voxels along its axis
+    (the voxels set to 2.0 in the current object)."""
+    base, centre, axis = patient_state
+    return cylinder_indices(base.shape, centre + shift_voxels * axis, axis, 1.0, 40.0)
+
+
 def serving_current(patient_state, shift_voxels: float):
     """The patient's object with the needle moved by shift_voxels along its axis."""
-    base, centre, axis = patient_state
-    cur = base.copy()
-    add_cylinder(cur, centre + shift_voxels * axis, axis, 1.0, 40.0, 2.0)
+    cur = patient_state[0].copy()
+    cur.reshape(-1)[serving_needle(patient_state, shift_voxels)] = 2.0
     return cur
 
 
