@@ -416,7 +416,9 @@ k_back(GeoK G, const float *__restrict__ yhat, float *__restrict__ out, const in
     const float xlo = (fi - 0.5f * G.nx) * G.hx, xhi = xlo + G.hx;
     const float ylo = (fj - 0.5f * G.ny) * G.hy, yhi = ylo + G.hy;
     const float fu_scale = G.dsd / G.du, fu_off = 0.5f * G.nu - 0.5f;
-    const float idv = 1.0f / G.dv, fv_off = 0.5f * G.nv - 0.5f;
+    // row index of height z at ray parameter A: z / (A dv) + nv/2 - 1/2; the
+    // 1e-3 margin (rows) is folded into the offset
+    const float a_ref_dv = a_ref * G.dv, fv_off = 0.5f * G.nv - 0.5f - 1e-3f;
     const float rwin = (float)(G.nv - C);  // last allowed window start
 
     for (int view = 0; view < G.nviews; ++view) {
@@ -434,8 +436,10 @@ k_back(GeoK G, const float *__restrict__ yhat, float *__restrict__ out, const in
             umin = fminf(umin, fu);
             umax = fmaxf(umax, fu);
         }
-        const int iu0 = max(0, (int)ceilf(umin - 1e-3f));
-        const int iu1 = min(G.nu - 1, (int)floorf(umax + 1e-3f));
+        // every lane computed the same range: keep it in scalar registers
+        const int iu0 = __builtin_amdgcn_readfirstlane(max(0, (int)ceilf(umin - 1e-3f)));
+        const int iu1 =
+            __builtin_amdgcn_readfirstlane(min(G.nu - 1, (int)floorf(umax + 1e-3f)));
         for (int iu = iu0; iu <= iu1; ++iu) {
             const float4 cxy = G.xy[(size_t)view * G.nu + iu];
             const float ex0 = plane_alpha(fi, cxy.x, cxy.y);
@@ -446,8 +450,8 @@ k_back(GeoK G, const float *__restrict__ yhat, float *__restrict__ out, const in
             const float ab = fminf(fmaxf(ex0, ex1), fmaxf(ey0, ey1));
             if (!(ab > aa)) continue;
             // heights reached by row v over the interval: z = A v, A in [A1, A2]
-            const float iA1 = __builtin_amdgcn_rcpf(a_ref + aa) * idv;
-            const float iA2 = __builtin_amdgcn_rcpf(a_ref + ab) * idv;
+            const float iA1 = __builtin_amdgcn_rcpf(fmaf(aa, G.dv, a_ref_dv));
+            const float iA2 = __builtin_amdgcn_rcpf(fmaf(ab, G.dv, a_ref_dv));
             const float *yrow = yhat + ((size_t)view * G.nu + iu) * G.nv;
 #pragma unroll
             for (int q = 0; q < QM; ++q) {
@@ -456,7 +460,7 @@ k_back(GeoK G, const float *__restrict__ yhat, float *__restrict__ out, const in
                 // rows kept inside [0, nv): every row meeting the cell is in it, and
                 // rows that miss the cell contribute exactly zero below
                 const float flo = fmaf(zk0[q], zk0[q] >= 0.0f ? iA2 : iA1, fv_off);
-                const int r0 = (int)fminf(fmaxf(ceilf(flo - 1e-3f), 0.0f), rwin);
+                const unsigned r0 = (unsigned)__builtin_amdgcn_fmed3f(ceilf(flo), 0.0f, rwin);
                 const float2 *zq = zrs + r0;
                 const float *yq = yrow + r0;
                 float a = acc[q];
@@ -472,7 +476,7 @@ k_back(GeoK G, const float *__restrict__ yhat, float *__restrict__ out, const in
                     const float hi = __builtin_amdgcn_fmed3f(ab, zA, zB);
                     a = fmaf(fmaxf(hi - lo, 0.0f), yq[c], a);
                 }
-                acc[q] = kok[q] ? a : 0.0f;
+                acc[q] = a;  // lanes past the column's end are never stored
             }
         }
     }
