@@ -463,11 +463,76 @@ def irn_piccs(g: Geometry, b, xp, x0, alpha, lam, tau, n_outer, n_inner,
     return IrnResult(x, hist, outs, broke)
 
 
+@dataclass
+class AugmentedPiple:
+    """IRN-PIPLE's augmented system (eq. "seq_W_2" written as one least-squares
+    problem): A~ = [A; alpha W1 D; lambda I] and b~ = [b; 0; lambda x_p].
+
+    Data-space tuples are (u_b, u_1, u_2) with u_1 of shape (3,) + volume shape
+    and u_2 of the volume shape.
+    """
+
+    g: Geometry
+    alpha: float
+    lam: float
+    w1: np.ndarray
+    A: object = None
+    AT: object = None
+
+    def forward(self, x):
+        Ax = self.A(x) if self.A is not None else forward(self.g, x)
+        return (Ax, self.alpha * self.w1[None] * D(x), self.lam * x)
+
+    def back(self, u):
+        ub, u1, u2 = u
+        ATu = self.AT(ub) if self.AT is not None else back(self.g, ub)
+        return ATu + self.alpha * DT(self.w1[None] * u1) + self.lam * u2
+
+    def rhs(self, b, xp):
+        return (np.asarray(b, dtype=np.float64), np.zeros((3,) + self.g.vol_shape),
+                self.lam * np.asarray(xp, dtype=np.float64).reshape(self.g.vol_shape))
+
+
+def irn_piple(g: Geometry, b, xp, x0, alpha, lam, tau, n_outer, n_inner,
+              reorth=False, A=None, AT=None, keep_iterates=False) -> IrnResult:
+    """IRN-PIPLE (eq. "seq_W_2"): TV(x) by IRN weights, ||x - x_p||^2 exactly.
+
+    Outer step k: W1 = W~(D x_{k-1}); then LSQR on [A; alpha W1 D; lambda I] x ~
+    [b; 0; lambda x_p] restarted from x_{k-1} gives x_k.
+    """
+    x = np.array(x0, dtype=np.float64, copy=True).reshape(g.vol_shape)
+    xp = np.asarray(xp, dtype=np.float64).reshape(g.vol_shape)
+    hist, outs = [], []
+    broke = False
+    for _k in range(n_outer):
+        w1 = weight_of_gradient(D(x), tau)
+        aug = AugmentedPiple(g, alpha, lam, w1, A=A, AT=AT)
+        res = lsqr(aug.forward, aug.back, aug.rhs(b, xp), x, n_inner, reorth=reorth)
+        x = res.x
+        hist.extend(res.phibar)
+        broke = broke or res.breakdown
+        if keep_iterates:
+            outs.append(x.copy())
+    return IrnResult(x, hist, outs, broke)
+
+
 def psi(s: np.ndarray, tau: float) -> np.ndarray:
     """psi(s) = 2 sqrt(s) - 2 tau^2 ln(1 + sqrt(s)/tau^2), so psi'(s) = 1/(sqrt(s) + tau^2)."""
     r = np.sqrt(s)
     t2 = tau * tau
     return 2.0 * r - 2.0 * t2 * np.log1p(r / t2)
+
+
+def piple_objective(g: Geometry, x, b, xp, alpha, lam, tau, A=None) -> float:
+    """F(x) = ||Ax-b||^2 + alpha^2 sum psi(|Dx|^2) + lambda^2 ||x - x_p||^2 (eq.
+    "PIRPLE_problem" with the smoothed TV whose tangent majorant is eq. "seq_W_2")."""
+    x = np.asarray(x, dtype=np.float64).reshape(g.vol_shape)
+    Ax = A(x) if A is not None else forward(g, x)
+    r = Ax - np.asarray(b, dtype=np.float64).reshape(Ax.shape)
+    s1 = (D(x) ** 2).sum(axis=0)
+    d = x - np.asarray(xp, dtype=np.float64).reshape(g.vol_shape)
+    return (float(np.vdot(r, r)) + alpha ** 2 * float(psi(s1, tau).sum())
+            + lam ** 2 * float(np.vdot(d, d)))
 
 
 def irn_objective(g: Geometry, x, b, xp, alpha, lam, tau, A=None) -> float:

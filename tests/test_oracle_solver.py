@@ -255,3 +255,67 @@ def test_irn_converges_to_a_stationary_point_of_F(orc):
 
     res = orc.irn_piccs(g, b, xp, x0, alpha, lam, tau, n_outer=60, n_inner=M, reorth=True)
     assert np.linalg.norm(grad(res.x)) < 1e-6 * np.linalg.norm(grad(x0))
+
+
+# ---------------------------------------------------------------- IRN-PIPLE (eq. seq_W_2)
+
+def test_piple_augmented_residual_and_adjoint(orc):
+    """||A~x - b~||^2 is the PIPLE quadratic of eq. seq_W_2, and A~^T is its adjoint."""
+    g = tiny(orc)
+    rng = np.random.default_rng(21)
+    x, xp, xk = rng.uniform(size=(3,) + g.vol_shape)
+    b = rng.uniform(size=g.proj_shape)
+    alpha, lam, tau = 0.7, 1.3, 0.2
+    w1 = orc.weight_of_gradient(orc.D(xk), tau)
+    aug = orc.AugmentedPiple(g, alpha, lam, w1)
+    r = tuple(p - q for p, q in zip(aug.forward(x), aug.rhs(b, xp)))
+    lhs = sum(float(np.vdot(p, p)) for p in r)
+    rhs = (float(np.sum((orc.forward(g, x) - b) ** 2))
+           + alpha ** 2 * float(np.sum((w1 * orc.D(x)) ** 2))
+           + lam ** 2 * float(np.sum((x - xp) ** 2)))
+    assert lhs == pytest.approx(rhs, rel=1e-13)
+    u = (rng.normal(size=g.proj_shape), rng.normal(size=(3,) + g.vol_shape),
+         rng.normal(size=g.vol_shape))
+    lhs = sum(float(np.vdot(p, q)) for p, q in zip(aug.forward(x), u))
+    assert lhs == pytest.approx(float(np.vdot(x, aug.back(u))), rel=1e-12)
+
+
+def test_piple_without_tv_is_tikhonov_towards_the_prior(orc):
+    """alpha = 0: one outer step solved to convergence is the solution of the
+    normal equations (A^T A + lambda^2 I) x = A^T b + lambda^2 x_p."""
+    g, xp, x0, b, _, lam, tau, _, _ = _problem(orc, seed=22)
+    M = g.nx * g.ny * g.nz
+    A = orc.dense_A(g)
+    x_ref = np.linalg.solve(A.T @ A + lam ** 2 * np.eye(M), A.T @ b.ravel() + lam ** 2 * xp.ravel())
+    res = orc.irn_piple(g, b, xp, x0, 0.0, lam, tau, 1, 2 * M, reorth=True)
+    np.testing.assert_allclose(res.x.ravel(), x_ref, rtol=1e-9, atol=1e-10)
+
+
+def test_piple_with_lambda_zero_is_irn_tv(orc):
+    g, xp, x0, b, alpha, _, tau, _, _ = _problem(orc, seed=23)
+    a = orc.irn_piple(g, b, xp, x0, alpha, 0.0, tau, 2, 5)
+    c = orc.irn_piccs(g, b, xp, x0, alpha, 0.0, tau, 2, 5)
+    np.testing.assert_allclose(a.x, c.x, rtol=1e-12, atol=1e-13)
+    np.testing.assert_allclose(a.phibar, c.phibar, rtol=1e-12)
+
+
+def test_piple_objective_descends_and_reaches_stationarity(orc):
+    """Majorise-minimise: F decreases every outer step, and with exact inner
+    solves the iterates reach grad F = 0, where
+    grad F(x) = 2 A^T(Ax - b) + 2 alpha^2 D^T(psi'(|Dx|^2) Dx) + 2 lambda^2 (x - x_p)."""
+    g, xp, x0, b, alpha, lam, tau, _, _ = _problem(orc, seed=24)
+    M = g.nx * g.ny * g.nz
+    res = orc.irn_piple(g, b, xp, x0, alpha, lam, tau, n_outer=8, n_inner=M, reorth=True,
+                        keep_iterates=True)
+    F = [orc.piple_objective(g, x0, b, xp, alpha, lam, tau)]
+    F += [orc.piple_objective(g, x, b, xp, alpha, lam, tau) for x in res.outer]
+    assert all(b_ <= a_ * (1 + 1e-12) for a_, b_ in zip(F, F[1:]))
+
+    def grad(x):
+        g1 = orc.D(x)
+        p1 = 1.0 / (np.sqrt((g1 ** 2).sum(0)) + tau * tau)
+        return 2 * (orc.back(g, orc.forward(g, x) - b, nthreads=1)
+                    + alpha ** 2 * orc.DT(p1[None] * g1) + lam ** 2 * (x - xp))
+
+    res = orc.irn_piple(g, b, xp, x0, alpha, lam, tau, n_outer=60, n_inner=M, reorth=True)
+    assert np.linalg.norm(grad(res.x)) < 1e-6 * np.linalg.norm(grad(x0))
