@@ -165,6 +165,12 @@ typedef enum {
     CBCT_PREC_MIXED_F16 = 2   /* scaled fp16 projector operands, fp32 accumulation   */
 } cbct_precision;
 
+/* The prior term (Sec. 2.1): PICCS penalises TV(x - x_p) (eq. "PICCS problem",
+ * third block lambda W2 D, right-hand side lambda W2 D x_p); PIPLE penalises
+ * ||x - x_p||_2^2 (eq. "PIRPLE_problem", solved by eq. "seq_W_2": third block
+ * lambda I, right-hand side lambda x_p; W2 is not used). */
+typedef enum { CBCT_METHOD_PICCS = 0, CBCT_METHOD_PIPLE = 1 } cbct_method;
+
 typedef struct {
     double alpha;     /* weight of TV(x)           (paper eq. "PICCS problem")   */
     double lambda;    /* weight of TV(x - x_p)                                    */
@@ -173,6 +179,7 @@ typedef struct {
     int32_t n_inner;  /* LSQR iterations per reweighting (total = outer * inner)  */
     int32_t precision;/* cbct_precision                                           */
     int32_t reorth;   /* 0: none (the paper's short recurrences); 1: reserved      */
+    int32_t method;   /* cbct_method: which prior term the third block encodes     */
 } piccs_params;
 
 typedef struct {
@@ -191,7 +198,9 @@ int piccs_workspace_bytes(const cbct_geom *g, const piccs_params *p, size_t *byt
  * problem): for k = 1..n_outer, W1 = W~(D x_{k-1}), W2 = W~(D x_{k-1} - D x_p),
  * then n_inner LSQR iterations (Paige & Saunders 1982) on
  *   [A; alpha W1 D; lambda W2 D] x ~ [b; 0; lambda W2 D x_p]
- * restarted from x_{k-1}.  The LSQR scalars (norms, Givens rotation) are kept
+ * restarted from x_{k-1}.  With p->method = CBCT_METHOD_PIPLE the third block is
+ * lambda I with right-hand side lambda x_p (IRN-PIPLE, Sec. 2.2.1, eq. "seq_W_2").
+ * lambda = 0 gives IRN-TV and alpha = lambda = 0 plain least squares.  The LSQR scalars (norms, Givens rotation) are kept
  * in FP64 on the device; the host never waits inside the solve.
  * b[view][v][u], xp and x[z][y][x] are float32 device arrays; x holds x_0 on
  * entry (warm start) and x_K on return.  workspace: >= piccs_workspace_bytes,

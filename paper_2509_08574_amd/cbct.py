@@ -20,6 +20,7 @@ OK, PENDING = 0, 1
 ERR_INVALID, ERR_OOM, ERR_DEVICE, ERR_BUSY, ERR_NOT_FOUND, ERR_NUMERIC = -1, -2, -3, -4, -5, -6
 F32, BF16, F16 = 0, 1, 2
 PREC_FP32, PREC_MIXED_BF16, PREC_MIXED_F16 = 0, 1, 2
+METHOD_PICCS, METHOD_PIPLE = 0, 1
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() "
@@ -52,7 +53,7 @@ class Params(ctypes.Structure):
     _fields_ = [("alpha", ctypes.c_double), ("lambda_", ctypes.c_double),
                 ("tau", ctypes.c_double), ("n_outer", ctypes.c_int32),
                 ("n_inner", ctypes.c_int32), ("precision", ctypes.c_int32),
-                ("reorth", ctypes.c_int32)]
+                ("reorth", ctypes.c_int32), ("method", ctypes.c_int32)]
 
 
 class Report(ctypes.Structure):
@@ -210,10 +211,11 @@ class SolveParams:
     n_inner: int
     precision: int = PREC_FP32
     reorth: int = 0
+    method: int = 0  # METHOD_PICCS or METHOD_PIPLE
 
     def c(self):
         return Params(self.alpha, self.lam, self.tau, self.n_outer, self.n_inner,
-                      self.precision, self.reorth)
+                      self.precision, self.reorth, self.method)
 
 
 def workspace_bytes(g: Geometry, p: SolveParams) -> int:

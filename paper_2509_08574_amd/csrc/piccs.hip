@@ -97,8 +97,9 @@ k_weights(GeoK G, const float *__restrict__ x, const float *__restrict__ xp, flo
 
 // (u1, u2) <- s1 * (alpha W1 D v, lambda W2 D(v - vp)) + s2 * (u1, u2)
 // (the second and third blocks of A~ v, or of b~ - A~ x when vp is given);
-// partial sums of |u1|^2 + |u2|^2 per block.
-template <bool HAS_VP>
+// partial sums of |u1|^2 + |u2|^2 per block.  PIPLE: the third block is
+// lambda (v - vp), one component per voxel (W2 unused).
+template <bool HAS_VP, bool PIPLE>
 __global__ void __launch_bounds__(256)
 k_regF(GeoK G, const float *__restrict__ V, const float *__restrict__ Vp,
        const float *__restrict__ W1, const float *__restrict__ W2, float *__restrict__ u1,
@@ -125,19 +126,25 @@ k_regF(GeoK G, const float *__restrict__ V, const float *__restrict__ Vp,
             d[2] = x0 - V[c + 1];
             e[2] = HAS_VP ? d[2] - (p0 - Vp[c + 1]) : d[2];
         }
-        const float a1 = alpha * W1[c], a2 = lam * W2[c];
+        const float a1 = alpha * W1[c], a2 = PIPLE ? lam : lam * W2[c];
         float acc = 0.f;
 #pragma unroll
         for (int q = 0; q < 3; ++q) {
             float n1 = s1 * (a1 * d[q]);
-            float n2 = s1 * (a2 * e[q]);
-            if (s2 != 0.0f) {
-                n1 = fmaf(s2, u1[c + q * cstride], n1);
-                n2 = fmaf(s2, u2[c + q * cstride], n2);
-            }
+            if (s2 != 0.0f) n1 = fmaf(s2, u1[c + q * cstride], n1);
             u1[c + q * cstride] = n1;
-            u2[c + q * cstride] = n2;
             acc = fmaf(n1, n1, acc);
+            if (!PIPLE) {
+                float n2 = s1 * (a2 * e[q]);
+                if (s2 != 0.0f) n2 = fmaf(s2, u2[c + q * cstride], n2);
+                u2[c + q * cstride] = n2;
+                acc = fmaf(n2, n2, acc);
+            }
+        }
+        if (PIPLE) {
+            float n2 = s1 * (a2 * (x0 - p0));
+            if (s2 != 0.0f) n2 = fmaf(s2, u2[c], n2);
+            u2[c] = n2;
             acc = fmaf(n2, n2, acc);
         }
         sum = (double)acc;
@@ -148,8 +155,10 @@ k_regF(GeoK G, const float *__restrict__ V, const float *__restrict__ Vp,
 // ---------------------------------------------------------------- regulariser, adjoint
 
 // v <- s1 * (t + alpha D^T(W1 u1) + lambda D^T(W2 u2)) + s2 * v, with t = A^T u-hat
-// from the back projector; partial sums of |v|^2 per block.
+// from the back projector; partial sums of |v|^2 per block.  PIPLE: the third
+// term is lambda u2 (one component per voxel).
 // D^T per axis: (D_1^T y)_i = y_i [i < n-1] - y_{i-1} [i >= 1].
+template <bool PIPLE>
 __global__ void __launch_bounds__(256)
 k_regA(GeoK G, const float *__restrict__ t, const float *__restrict__ W1,
        const float *__restrict__ W2, const float *__restrict__ u1, const float *__restrict__ u2,
@@ -164,21 +173,20 @@ k_regA(GeoK G, const float *__restrict__ t, const float *__restrict__ W1,
         const int64_t st[3] = {G.Z, (int64_t)G.nx * G.Z, 1};
         const bool hi[3] = {v.i < G.nx - 1, v.j < G.ny - 1, v.k < G.nz - 1};
         const bool lo[3] = {v.i > 0, v.j > 0, v.k > 0};
-        const float w1c = W1[c], w2c = W2[c];
+        const float w1c = W1[c];
         float r1 = 0.f, r2 = 0.f;
 #pragma unroll
         for (int q = 0; q < 3; ++q) {
             const float *a = u1 + q * cstride;
-            const float *b = u2 + q * cstride;
-            if (hi[q]) {
-                r1 += w1c * a[c];
-                r2 += w2c * b[c];
-            }
-            if (lo[q]) {
-                r1 -= W1[c - st[q]] * a[c - st[q]];
-                r2 -= W2[c - st[q]] * b[c - st[q]];
+            if (hi[q]) r1 += w1c * a[c];
+            if (lo[q]) r1 -= W1[c - st[q]] * a[c - st[q]];
+            if (!PIPLE) {
+                const float *b = u2 + q * cstride;
+                if (hi[q]) r2 += W2[c] * b[c];
+                if (lo[q]) r2 -= W2[c - st[q]] * b[c - st[q]];
             }
         }
+        if (PIPLE) r2 = u2[c];
         float vn = s1 * (t[c] + alpha * r1 + lam * r2);
         if (s2 != 0.0f) vn = fmaf(s2, V[c], vn);
         V[c] = vn;
@@ -386,6 +394,8 @@ void check_solve_params(const piccs_params *p) {
                      p->precision == CBCT_PREC_MIXED_F16,
                  "unknown precision");
     CBCT_REQUIRE(p->reorth == 0, "reorthogonalisation is not available in this build");
+    CBCT_REQUIRE(p->method == CBCT_METHOD_PICCS || p->method == CBCT_METHOD_PIPLE,
+                 "unknown method");
 }
 
 // Enqueues one whole IRN-PICCS solve on stream s (no host synchronisation).
@@ -403,6 +413,10 @@ void solve_enqueue(cbct_geom *g, const float *b, const float *xp, float *x,
     const unsigned nvb = (unsigned)vox_blocks(G);
     const float alpha = (float)p->alpha, lam = (float)p->lambda;
     const float tau2 = (float)(p->tau * p->tau);
+    const bool piple = p->method == CBCT_METHOD_PIPLE;
+    auto regF_init = piple ? k_regF<true, true> : k_regF<true, false>;
+    auto regF_step = piple ? k_regF<false, true> : k_regF<false, false>;
+    auto regA = piple ? k_regA<true> : k_regA<false>;
 
     // padded column copies of the inputs (pads and guards zero)
     launch_fill(W.x - kGuard, W.cstride * 13, 0.0f, s);
@@ -441,14 +455,14 @@ void solve_enqueue(cbct_geom *g, const float *b, const float *xp, float *x,
         // beta_1 u_1 = b~ - A~ x_{k-1}
         fa.vol = W.x; fa.uin = W.bhat; fa.s1 = W.sc + SC_M1; fa.s2 = W.sc + SC_P1;
         launch_forward(G, FWD_SOLVER, fa, s);
-        hipLaunchKernelGGL(k_regF<true>, dim3(nvb), dim3(256), 0, s, G, W.x, W.xp, W.W1,
+        hipLaunchKernelGGL(regF_init, dim3(nvb), dim3(256), 0, s, G, W.x, W.xp, W.W1,
                            W.W2, W.u1, W.u2, W.cstride, alpha, lam, W.sc + SC_M1,
                            W.sc + SC_ZERO, W.pr, W.fl);
         hipLaunchKernelGGL(k_red<RED_INIT_BETA>, dim3(1), dim3(1024), 0, s, W.pf, W.nf,
                            W.pr, W.nr, W.sc, W.fl, W.hist, 0, dt, nvox);
         // alpha_1 v_1 = A~^T u_1
         launch_back(G, W.uhat, W.t, W.fl, s);
-        hipLaunchKernelGGL(k_regA, dim3(nvb), dim3(256), 0, s, G, W.t, W.W1, W.W2, W.u1,
+        hipLaunchKernelGGL(regA, dim3(nvb), dim3(256), 0, s, G, W.t, W.W1, W.W2, W.u1,
                            W.u2, W.cstride, alpha, lam, W.V, W.sc + SC_BACK_S1,
                            W.sc + SC_BACK_S2, W.pa, W.fl);
         hipLaunchKernelGGL(k_red<RED_INIT_ALPHA>, dim3(1), dim3(1024), 0, s, W.pa, W.nr,
@@ -459,13 +473,13 @@ void solve_enqueue(cbct_geom *g, const float *b, const float *xp, float *x,
             fa.vol = dt == CBCT_F32 ? (const void *)W.V : (const void *)W.V16;
             fa.uin = W.uhat; fa.s1 = W.sc + SC_FWD_S1; fa.s2 = W.sc + SC_FWD_S2;
             launch_forward(G, FWD_SOLVER, fa, s, dt);
-            hipLaunchKernelGGL(k_regF<false>, dim3(nvb), dim3(256), 0, s, G, W.V,
+            hipLaunchKernelGGL(regF_step, dim3(nvb), dim3(256), 0, s, G, W.V,
                                (const float *)nullptr, W.W1, W.W2, W.u1, W.u2, W.cstride,
                                alpha, lam, W.sc + SC_REG_S1, W.sc + SC_REG_S2, W.pr, W.fl);
             hipLaunchKernelGGL(k_red<RED_BETA>, dim3(1), dim3(1024), 0, s, W.pf, W.nf,
                                W.pr, W.nr, W.sc, W.fl, W.hist, it_global, dt, nvox);
             launch_back(G, W.uhat, W.t, W.fl, s);
-            hipLaunchKernelGGL(k_regA, dim3(nvb), dim3(256), 0, s, G, W.t, W.W1, W.W2, W.u1,
+            hipLaunchKernelGGL(regA, dim3(nvb), dim3(256), 0, s, G, W.t, W.W1, W.W2, W.u1,
                                W.u2, W.cstride, alpha, lam, W.V, W.sc + SC_BACK_S1,
                                W.sc + SC_BACK_S2, W.pa, W.fl);
             hipLaunchKernelGGL(k_red<RED_ALPHA>, dim3(1), dim3(1024), 0, s, W.pa, W.nr,

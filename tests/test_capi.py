@@ -64,8 +64,11 @@ def test_workspace_bytes_and_param_checks(lib):
     pad = (64 * 64 * 66 + 128) * 4
     assert n >= 13 * pad + 2 * 48 * 96 * 96 * 4
     assert n < 13 * pad + 2 * 48 * 96 * 96 * 4 + 8 * 1024 * 1024
+    assert lib.workspace_bytes(g, lib.SolveParams(1.0, 2.0, 0.1, 3, 5,
+                                                  method=lib.METHOD_PIPLE)) == n
     for bad in (lib.SolveParams(-1.0, 2.0, 0.1, 3, 5), lib.SolveParams(1.0, 2.0, 0.1, 0, 5),
-                lib.SolveParams(1.0, 2.0, float("nan"), 3, 5)):
+                lib.SolveParams(1.0, 2.0, float("nan"), 3, 5),
+                lib.SolveParams(1.0, 2.0, 0.1, 3, 5, method=2)):
         with pytest.raises(lib.CbctError):
             lib.workspace_bytes(g, bad)
 

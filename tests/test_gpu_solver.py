@@ -163,3 +163,49 @@ def test_mixed_forms_on_ragged_geometry(orc, lib):
     for pr in (lib.PREC_MIXED_BF16, lib.PREC_MIXED_F16):
         xg, _ = _gpu_solve(lib, d, b, xp, xp, lib.SolveParams(0.5, 1.5, 0.2, 2, 4, precision=pr))
         assert rel(xg, ref.x) <= 1e-3
+
+
+# ---------------------------------------------------------------- IRN-PIPLE
+
+def test_c1_irn_piple_parity(orc, lib):
+    """Third block lambda I, right-hand side lambda x_p (eq. seq_W_2)."""
+    d, og, prior, cur, b, sp = c1_inputs(orc)
+    ref = orc.irn_piple(og, b, prior, prior, sp["alpha"], sp["lam"], sp["tau"], sp["n_outer"],
+                        sp["n_inner"])
+    p = lib.SolveParams(sp["alpha"], sp["lam"], sp["tau"], sp["n_outer"], sp["n_inner"],
+                        method=lib.METHOD_PIPLE)
+    xg, rep = _gpu_solve(lib, d, b, prior, prior, p)
+    assert rep["inner_done"] == sp["n_outer"] * sp["n_inner"] and rep["breakdown"] == 0
+    assert rel(xg, ref.x) <= SOLVE_TOL
+    np.testing.assert_allclose(rep["phibar"], ref.phibar, rtol=SOLVE_TOL)
+    assert np.linalg.norm(xg - cur) < np.linalg.norm(prior - cur)
+
+
+def test_piple_and_piccs_agree_without_the_prior_term(orc, lib):
+    """lambda = 0 leaves IRN-TV in both methods: identical results."""
+    d, og, prior, cur, b, sp = c1_inputs(orc)
+    x1, r1 = _gpu_solve(lib, d, b, prior, prior, lib.SolveParams(sp["alpha"], 0.0, sp["tau"], 2, 4))
+    x2, r2 = _gpu_solve(lib, d, b, prior, prior,
+                        lib.SolveParams(sp["alpha"], 0.0, sp["tau"], 2, 4,
+                                        method=lib.METHOD_PIPLE))
+    assert np.array_equal(x1, x2)
+    assert r1["phibar"] == r2["phibar"]
+
+
+def test_piple_on_ragged_geometry_and_mixed(orc, lib):
+    rng = np.random.default_rng(29)
+    d = dict(nx=21, ny=19, nz=17, vx=1.0, vy=1.0, vz=1.0, nu=37, nv=150, du=1.1, dv=0.45,
+             dso=80.0, dsd=130.0, n_views=13)
+    og = orc.Geometry.from_dict(d)
+    xp = rng.uniform(size=og.vol_shape).astype(np.float32).astype(np.float64)
+    xt = xp + 0.3 * (rng.uniform(size=og.vol_shape) > 0.9)
+    b = orc.forward(og, xt).astype(np.float32).astype(np.float64)
+    ref = orc.irn_piple(og, b, xp, xp, 0.5, 1.5, 0.2, 2, 4)
+    xg, _ = _gpu_solve(lib, d, b, xp, xp,
+                       lib.SolveParams(0.5, 1.5, 0.2, 2, 4, method=lib.METHOD_PIPLE))
+    assert rel(xg, ref.x) <= SOLVE_TOL
+    for pr in (lib.PREC_MIXED_BF16, lib.PREC_MIXED_F16):
+        xg, _ = _gpu_solve(lib, d, b, xp, xp,
+                           lib.SolveParams(0.5, 1.5, 0.2, 2, 4, precision=pr,
+                                           method=lib.METHOD_PIPLE))
+        assert rel(xg, ref.x) <= 1e-3
