@@ -156,6 +156,23 @@ int cbct_back_cols(const cbct_geom *g, const float *ywcols, float *cols, void *h
 int piccs_weights(const cbct_geom *g, const float *x, const float *xp, double tau, float *w1,
                   float *w2, void *hip_stream);
 
+/*
+ * FDK reconstruction (Feldkamp, Davis & Kress 1984), the direct cone-beam
+ * method of the clinical flow (Sec. 3 compares against it): a first image when
+ * no prior exists.  y[view][v][u] line integrals -> x[z][y][x]:
+ *   1. weight each sample by DSD / sqrt(DSD^2 + u^2 + v^2);
+ *   2. convolve each detector row along u with the band-limited ramp filter at
+ *      the isocentre pitch dp = du DSO / DSD;
+ *   3. x(r) = sum over views of (dbeta/2) (DSO/U)^2 Q(u(r), v(r)), U the depth
+ *      of r along the central ray, bilinear interpolation, zero outside the
+ *      detector; dbeta is half the angle between a view's two neighbours on
+ *      the circle (2 pi / V for equal spacing).
+ * Full 360-degree scans.  Device pointers; a temporary of (N + M) floats is
+ * taken from the stream's memory pool.  Errors: CBCT_ERR_INVALID (null pointer,
+ * nu > 1900), CBCT_ERR_OOM, CBCT_ERR_DEVICE.
+ */
+int cbct_fdk(const cbct_geom *g, const float *y, float *x, void *hip_stream);
+
 /* ------------------------------------------------------------------------ */
 /* IRN-PICCS Krylov solve                                                    */
 

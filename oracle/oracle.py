@@ -636,6 +636,38 @@ def fdk_backproject(g: Geometry, q: np.ndarray) -> np.ndarray:
     return out
 
 
+def fdk_backproject_at(g: Geometry, q: np.ndarray, flat_idx) -> np.ndarray:
+    """fdk_backproject evaluated only at the voxels with flat [z][y][x] indices
+    flat_idx (same formula, one voxel at a time)."""
+    V, nv, nu = g.proj_shape
+    q = np.asarray(q, dtype=np.float64).reshape(V, nv, nu)
+    wv = fdk_view_weights(g)
+    out = np.zeros(len(flat_idx))
+    for n, f in enumerate(flat_idx):
+        k, rem = divmod(int(f), g.nx * g.ny)
+        j, i = divmod(rem, g.nx)
+        X = (i + 0.5) * g.vx - 0.5 * g.nx * g.vx
+        Y = (j + 0.5) * g.vy - 0.5 * g.ny * g.vy
+        Zc = (k + 0.5) * g.vz - 0.5 * g.nz * g.vz
+        acc = 0.0
+        for v, th in enumerate(g.angles):
+            c, s = math.cos(th), math.sin(th)
+            U = g.dso - (X * c + Y * s)
+            fu = g.dsd * (-X * s + Y * c) / U / g.du + 0.5 * nu - 0.5
+            fv = g.dsd * Zc / U / g.dv + 0.5 * nv - 0.5
+            i0, j0 = math.floor(fu), math.floor(fv)
+            au, av = fu - i0, fv - j0
+            val = 0.0
+            for di, wu in ((0, 1.0 - au), (1, au)):
+                for dj, wvv in ((0, 1.0 - av), (1, av)):
+                    ii, jj = i0 + di, j0 + dj
+                    if 0 <= ii < nu and 0 <= jj < nv:
+                        val += wu * wvv * q[v, jj, ii]
+            acc += 0.5 * wv[v] * (g.dso / U) ** 2 * val
+        out[n] = acc
+    return out
+
+
 def fdk(g: Geometry, y: np.ndarray) -> np.ndarray:
     """FDK reconstruction of line-integral projections y[view][v][u]."""
     return fdk_backproject(g, fdk_filter(g, y))

@@ -34,7 +34,7 @@ EXPORTS = ["cbct_last_error", "cbct_geom_create", "cbct_geom_destroy", "cbct_geo
            "cbct_cols_to_vol", "cbct_proj_to_cols", "cbct_cols_to_proj", "cbct_forward_cols",
            "cbct_back_cols", "cbct_server_create", "cbct_server_add_prior", "cbct_server_submit",
            "cbct_server_poll", "cbct_server_stats_get", "cbct_server_destroy",
-           "cbct_server_footprint"]
+           "cbct_server_footprint", "cbct_fdk"]
 
 
 class GeomDesc(ctypes.Structure):
@@ -76,6 +76,19 @@ _lib.piccs_workspace_bytes.argtypes = [_vp, ctypes.POINTER(Params),
                                        ctypes.POINTER(ctypes.c_size_t)]
 _lib.piccs_krylov_solve.argtypes = [_vp, _vp, _vp, _vp, ctypes.POINTER(Params), _vp,
                                     ctypes.c_size_t, ctypes.POINTER(Report), _vp]
+
+
+_lib.cbct_fdk.argtypes = [_vp, _vp, _vp, _vp]
+
+
+def fdk(g: "Geometry", y: torch.Tensor, x: torch.Tensor | None = None, stream=None):
+    """cbct_fdk: FDK reconstruction of line integrals y[view][v][u] into x[z][y][x]."""
+    _need(y, g.proj_shape)
+    if x is None:
+        x = torch.empty(g.vol_shape, dtype=torch.float32, device=y.device)
+    _need(x, g.vol_shape)
+    _check(_lib.cbct_fdk(g.handle, _ptr(y), _ptr(x), _stream(stream)))
+    return x
 
 
 _i64p = ctypes.POINTER(ctypes.c_int64)

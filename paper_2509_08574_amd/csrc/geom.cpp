@@ -1,4 +1,5 @@
 // Geometry handle: validation, float64 -> float32 ray tables, per-device upload.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 
@@ -71,6 +72,33 @@ static void build_tables(cbct_geom *g) {
         const double u = (iu + 0.5) * d.du - d.nu * d.du / 2.0;
         g->Lu2[(size_t)iu] = (float)(d.dsd * d.dsd + u * u);
     }
+    // FDK quadrature: each view weighs half the angle between its neighbours
+    // on the circle (2 pi / V for equal spacing); half of that again is the
+    // 1/2 of the full-scan formula.
+    {
+        const double two_pi = 2.0 * M_PI;
+        std::vector<std::pair<double, int>> a((size_t)d.n_views);
+        for (int v = 0; v < d.n_views; ++v)
+            a[(size_t)v] = {std::fmod(std::fmod(g->angles[(size_t)v], two_pi) + two_pi, two_pi),
+                            v};
+        std::sort(a.begin(), a.end());
+        g->fdkw.resize((size_t)d.n_views);
+        for (int q = 0; q < d.n_views; ++q) {
+            const double nxt = q + 1 < d.n_views ? a[(size_t)q + 1].first : a[0].first + two_pi;
+            const double prv = q > 0 ? a[(size_t)q - 1].first : a.back().first - two_pi;
+            g->fdkw[(size_t)a[(size_t)q].second] = (float)(0.25 * (nxt - prv));
+        }
+    }
+    // band-limited ramp at the isocentre pitch, times that pitch
+    {
+        const double dp = d.du * d.dso / d.dsd;
+        g->ramp.resize((size_t)d.nu / 2 + 1);
+        g->ramp[0] = (float)(1.0 / (4.0 * dp));
+        for (size_t m = 0; m + 1 < g->ramp.size(); ++m) {
+            const double n = 2.0 * (double)m + 1.0;
+            g->ramp[m + 1] = (float)(-1.0 / (n * n * M_PI * M_PI * dp));
+        }
+    }
 }
 
 static void validate(const cbct_geom_desc *d) {
@@ -111,12 +139,13 @@ static GeoK make_geok(const cbct_geom *g, const DevTables &t) {
     G.dso = (float)d.dso; G.dsd = (float)d.dsd; G.du = (float)d.du; G.dv = (float)d.dv;
     G.xy = t.xy; G.xy0 = t.xy0; G.zr = t.zr; G.Lu2 = t.Lu2; G.Lv2 = t.Lv2; G.trig = t.trig;
     G.seghdr = t.seghdr; G.seg = t.seg; G.seg_stride = d.nx + d.ny - 1 + kSegPad;
+    G.fdkw = t.fdkw; G.ramp = t.ramp;
     return G;
 }
 
 // Offsets of the device tables inside one block, each part 256-byte aligned.
 struct TableLayout {
-    size_t xy, xy0, zr, Lu2, Lv2, trig, seghdr, seg, total;
+    size_t xy, xy0, zr, Lu2, Lv2, trig, seghdr, seg, fdkw, ramp, total;
 };
 
 static TableLayout table_layout(const cbct_geom_desc &d) {
@@ -137,6 +166,8 @@ static TableLayout table_layout(const cbct_geom_desc &d) {
     L.trig = put(sizeof(float2) * d.n_views);
     L.seghdr = put(sizeof(int2) * nr);
     L.seg = put(sizeof(int2) * nr * stride);
+    L.fdkw = put(sizeof(float) * d.n_views);
+    L.ramp = put(sizeof(float) * ((size_t)d.nu / 2 + 1));
     L.total = o;
     return L;
 }
@@ -155,6 +186,8 @@ static void upload_tables(cbct_geom *g, char *base, DevTables &t, hipStream_t s)
     t.trig = (float2 *)(base + L.trig);
     t.seghdr = (int2 *)(base + L.seghdr);
     t.seg = (int2 *)(base + L.seg);
+    t.fdkw = (float *)(base + L.fdkw);
+    t.ramp = (float *)(base + L.ramp);
     CBCT_HIP(hipMemcpyAsync(t.xy, g->xy.data(), sizeof(float4) * g->xy.size(),
                             hipMemcpyHostToDevice, s));
     CBCT_HIP(hipMemcpyAsync(t.xy0, g->xy0.data(), sizeof(float2) * g->xy0.size(),
@@ -164,6 +197,10 @@ static void upload_tables(cbct_geom *g, char *base, DevTables &t, hipStream_t s)
     CBCT_HIP(hipMemcpyAsync(t.Lu2, g->Lu2.data(), sizeof(float) * d.nu, hipMemcpyHostToDevice, s));
     CBCT_HIP(hipMemcpyAsync(t.Lv2, g->Lv2.data(), sizeof(float) * d.nv, hipMemcpyHostToDevice, s));
     CBCT_HIP(hipMemcpyAsync(t.trig, g->trig.data(), sizeof(float2) * g->trig.size(),
+                            hipMemcpyHostToDevice, s));
+    CBCT_HIP(hipMemcpyAsync(t.fdkw, g->fdkw.data(), sizeof(float) * g->fdkw.size(),
+                            hipMemcpyHostToDevice, s));
+    CBCT_HIP(hipMemcpyAsync(t.ramp, g->ramp.data(), sizeof(float) * g->ramp.size(),
                             hipMemcpyHostToDevice, s));
     GeoK G = make_geok(g, t);
     launch_segment_tables(G, t.seghdr, t.seg, s);

@@ -67,6 +67,11 @@ struct GeoK {
     const int2 *seghdr;  // [nviews*nu]
     const int2 *seg;     // [nviews*nu*seg_stride]
     int seg_stride;      // nx + ny - 1 + kSegPad (at most nx + ny - 1 segments)
+    // FDK: half the angular quadrature weight of each view, and the ramp
+    // filter's non-zero taps times the isocentre pitch dp:
+    // ramp[0] = 1/(4 dp) (tap 0), ramp[m+1] = -1/((2m+1)^2 pi^2 dp) (taps +-(2m+1)).
+    const float *fdkw;   // [nviews]
+    const float *ramp;   // [nu/2 + 1]
 };
 
 constexpr int kSegPad = 4;
@@ -80,6 +85,8 @@ struct DevTables {
     float2 *trig = nullptr;
     int2 *seghdr = nullptr;
     int2 *seg = nullptr;
+    float *fdkw = nullptr;
+    float *ramp = nullptr;
     void *block = nullptr;   // one allocation holding all of the above
     bool external = false;   // block owned by the caller of geo_place
 };
@@ -95,6 +102,7 @@ struct cbct_geom {
     std::vector<float4> zr;
     std::vector<float> Lu2, Lv2;
     std::vector<float2> trig;
+    std::vector<float> fdkw, ramp;
     std::mutex mu;
     std::map<int, cbct::DevTables> dev;
 

@@ -124,3 +124,13 @@ def test_server_create_without_a_device_fails_cleanly(lib):
     h = ctypes.c_void_p()
     rc = lib._lib.cbct_server_create(ctypes.byref(cfg), ctypes.byref(h))
     assert rc in (lib.ERR_INVALID, lib.ERR_DEVICE) and not h.value
+
+
+def test_fdk_argument_checks(lib):
+    g = lib.Geometry(**C1)
+    so = lib._lib
+    assert so.cbct_fdk(g.handle, None, None, None) == lib.ERR_INVALID
+    wide = lib.Geometry(**dict(C1, nu=2048, du=0.07))
+    assert so.cbct_fdk(wide.handle, ctypes.c_void_p(16), ctypes.c_void_p(16), None) == \
+        lib.ERR_INVALID
+    assert "too long" in lib.last_error()

@@ -215,15 +215,16 @@ def test_refusals(orc, lib):
 
 
 def test_queue_limit(orc, lib):
-    g = geom(32, 20)
-    xp = patient(orc, 6, 32)
+    # requests long enough (64^3, 60 views, 3 x 20) that submitting 50 in a row
+    # outpaces the device by far
+    g = geom(64, 60)
+    xp = patient(orc, 6, 64)
     b = request_b(orc, g, xp, 2.0, 61)
-    p = lib.SolveParams(**PARAMS)
+    p = lib.SolveParams(1.0, 1.0, 0.1, 3, 20)
     with lib.Server(hbm_budget_bytes=1 << 30, max_slots=1, max_queue=2) as srv:
         srv.add_prior(6, g, xp)
-        # one slot, two waiting: submitting faster than a solve finishes must
-        # hit the limit after two accepted requests (none admitted yet) or
-        # three (the first already on the device)
+        # one slot, two waiting: the limit is hit after two accepted requests
+        # (none admitted yet) or three (the first already on the device)
         got, busy = [], False
         for _ in range(50):
             try:

@@ -103,3 +103,13 @@ def test_fdk_distance_weighting_far_from_the_axis(orc):
     inside = r < radius - 3.0
     assert inside.sum() > 20
     assert abs(x[inside].mean() - rho) < 0.04 * rho
+
+
+def test_sampled_backprojection_matches_the_full_one(orc):
+    g = orc.Geometry(nx=9, ny=8, nz=7, vx=1, vy=1, vz=1, nu=14, nv=12, du=1.1, dv=1.1, dso=60,
+                     dsd=100, n_views=11)
+    q = np.random.default_rng(5).normal(size=g.proj_shape)
+    full = orc.fdk_backproject(g, q).ravel()
+    idx = np.random.default_rng(6).choice(full.size, 40, replace=False)
+    np.testing.assert_allclose(orc.fdk_backproject_at(g, q, idx), full[idx], rtol=1e-12,
+                               atol=1e-12)
