@@ -254,6 +254,74 @@ def serving_bench(args, cbct, synth, np, torch, dev):
     }
 
 
+def quality_bench(args, cbct, synth, np, torch, dev):
+    """Stand-ins for the paper's two experiments (Sec. 3): head with a cubic
+    tumour (20 views, noise-free projections) and thorax with a needle (180 / 50 /
+    20 views, Poisson noise at I0 = 5e4).  FDK, plain least squares (LSQR, 20
+    iterations), IRN-TV, IRN-PIPLE and IRN-PICCS (alpha = lambda = 1, tau = 0.1;
+    25 inner iterations per outer step, errors after 1..4 outer steps).  PSNR,
+    SSIM and relative L2 error against the ground truth over the whole volume."""
+    from paper_2509_08574_amd import metrics
+    cases = [("head", synth.head_case, synth.head_geometry, [20], None)]
+    if not args.quality_head_only:
+        cases.append(("thorax", synth.thorax_case, synth.thorax_geometry, [180, 50, 20], 5e4))
+    out = {}
+    gen = torch.Generator(device=dev)
+    for name, make, geom, views, I0 in cases:
+        prior, truth = make()
+        xp_d = torch.from_numpy(prior.astype(np.float32)).to(dev)
+        tr_d = torch.from_numpy(truth.astype(np.float32)).to(dev)
+        for V in views:
+            gd = geom(V)
+            g = cbct.Geometry.from_dict(gd)
+            y = cbct.forward(g, tr_d)
+            if I0:
+                gen.manual_seed(1000 + V)
+                lam = I0 * torch.exp(-synth.MU_WATER_PER_MM * y.double())
+                counts = torch.clamp(torch.poisson(lam, generator=gen), min=1.0)
+                y = (-torch.log(counts / I0) / synth.MU_WATER_PER_MM).float()
+            rows = []
+
+            def record(label, iters, x, sec):
+                xh = x.detach().cpu().numpy().astype(np.float64)
+                rows.append({"method": label, "iterations": iters, "time_s": round(sec, 4),
+                             "psnr": round(metrics.psnr(xh, truth), 3),
+                             "ssim": round(metrics.ssim(xh, truth), 4),
+                             "rel_l2": round(metrics.rel_l2(xh, truth), 5)})
+                log(f"[quality] {name} {V} views {label:10s} {iters:>14s}: PSNR "
+                    f"{rows[-1]['psnr']:.2f} SSIM {rows[-1]['ssim']:.4f} "
+                    f"rel {rows[-1]['rel_l2']:.4f} ({sec * 1e3:.0f} ms)")
+
+            def timed(fn):
+                torch.cuda.synchronize()
+                t = time.perf_counter()
+                r = fn()
+                torch.cuda.synchronize()
+                return r, time.perf_counter() - t
+
+            xf, sec = timed(lambda: cbct.fdk(g, y))
+            record("FDK", "-", xf, sec)
+            zero = torch.zeros_like(xp_d)
+
+            def solve(x0, p):
+                x = x0.clone()
+                cbct.solve(g, y, xp_d, x, p, report=False)
+                return x
+            xl, sec = timed(lambda: solve(zero, cbct.SolveParams(0.0, 0.0, 0.1, 1, 20)))
+            record("LSQR", "20", xl, sec)
+            for label, lam_, meth, x0 in (("IRN-TV", 0.0, cbct.METHOD_PICCS, zero),
+                                         ("IRN-PIPLE", 1.0, cbct.METHOD_PIPLE, xp_d),
+                                         ("IRN-PICCS", 1.0, cbct.METHOD_PICCS, xp_d)):
+                for k in (1, 2, 3, 4):
+                    p = cbct.SolveParams(1.0, lam_, 0.1, k, 25, method=meth)
+                    xk, sec = timed(lambda: solve(x0, p))
+                    record(label, f"{25 * k} ({k} outer)", xk, sec)
+            record("prior x_p", "-", xp_d, 0.0)
+            out[f"{name}_{V}views"] = rows
+            g.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -268,6 +336,9 @@ def main():
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also run one plain device copy of this many MiB (profiler calibration)")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving stream")
+    ap.add_argument("--quality", action="store_true",
+                    help="only the head / thorax stand-in quality table (PSNR, SSIM)")
+    ap.add_argument("--quality-head-only", action="store_true")
     ap.add_argument("--ops-only", action="store_true",
                     help="time only the projector pair on random data (profiler passes)")
     ap.add_argument("--serve-only", action="store_true",
@@ -317,6 +388,10 @@ def main():
         return
     if args.serve_only:
         print(json.dumps({"serving": serving_bench(args, cbct, synth, np, torch, dev)}),
+              flush=True)
+        return
+    if args.quality:
+        print(json.dumps({"quality": quality_bench(args, cbct, synth, np, torch, dev)}),
               flush=True)
         return
     wl = args.workload
@@ -415,6 +490,19 @@ def main():
             log(f"[bench] {name}: {sec * 1e3:.1f} ms/recon")
     forms["fp32"] = {"s_per_recon": round(ms_per_step / 1e3, 4), "speedup_vs_fp32": 1.0}
 
+    # ---------------- FDK of the same scan (direct method, no prior)
+    xf = cbct.fdk(g, b_d, stream=stream)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    for _ in range(args.op_reps):
+        cbct.fdk(g, b_d, xf, stream=stream)
+    ev1.record(stream)
+    ev1.synchronize()
+    fdk_ms = ev0.elapsed_time(ev1) / args.op_reps
+    err_fdk = float(torch.linalg.norm(xf - cur_d) / torch.linalg.norm(cur_d))
+    log(f"[bench] FDK {fdk_ms:.2f} ms, rel err vs truth {err_fdk:.4f}")
+    del xf
+
     # ---------------- isolated projector kernels (HIP events on this stream)
     xc = cbct.vol_to_cols(g, cur_d)
     ywc = cbct.proj_to_cols(g, b_d, weighted=True)
@@ -505,6 +593,8 @@ def main():
             "nnz": nnz,
             "rel_err_vs_truth": round(err_truth, 5),
             "rel_err_prior_vs_truth": round(err_prior, 5),
+            "fdk_ms": round(fdk_ms, 3),
+            "rel_err_fdk_vs_truth": round(err_fdk, 5),
             "prior": args.prior,
         },
         "precision_forms": forms,

@@ -243,3 +243,63 @@ def serving_request_draw(i: int, n_patients: int):
     rng = np.random.default_rng(4000 + i)
     return (int(rng.integers(n_patients)), int(rng.integers(30, 121)),
             float(rng.uniform(2.0, 5.0)))
+
+
+# --------------------------------------------------------------------------
+# Stand-ins shaped like the paper's two experiments (Sec. 3), whose data are
+# not available: a digital head with a cubic tumour (128^3, 128^2 detector, 20
+# views) and a thorax with a needle (256^3, 512 x 364 detector at 0.776 mm,
+# DSO 810, DSD 1195, 20 / 50 / 180 views).  Densities are relative to water.
+
+def head_geometry(n_views: int = 20) -> dict:
+    """128^3 at 1.6 mm, 128^2 detector at 2.4 mm (the head's geometry is not
+    stated; these distances are the common 1000 / 1536 mm)."""
+    return dict(nx=128, ny=128, nz=128, vx=1.6, vy=1.6, vz=1.6, nu=128, nv=128, du=2.4,
+                dv=2.4, dso=1000.0, dsd=1536.0, n_views=n_views)
+
+
+def head_case(seed: int = 31):
+    """(prior, current): skull shell around brain tissue with seeded internal
+    structures; the current scan adds an 8 x 8 x 8-voxel cubic tumour."""
+    rng = np.random.default_rng(seed)
+    n = 128
+    vol = np.zeros((n, n, n))
+    c = np.array([64.0, 64.0, 64.0])
+    add_ellipsoid(vol, c, (46.0, 56.0, 50.0), np.eye(3), 1.6)    # skull
+    add_ellipsoid(vol, c, (42.0, 52.0, 46.0), np.eye(3), -0.6)   # brain = 1.0
+    for _ in range(14):                                           # internal structure
+        cc = c + rng.uniform(-28, 28, size=3)
+        add_ellipsoid(vol, cc, rng.uniform(3.0, 12.0, size=3), _rotation(rng),
+                      rng.uniform(-0.12, 0.12))
+    cur = vol.copy()
+    t0 = (c + rng.uniform(-18, 18, size=3)).astype(int) - 4
+    cur[t0[2]:t0[2] + 8, t0[1]:t0[1] + 8, t0[0]:t0[0] + 8] += 0.15
+    return vol, cur
+
+
+def thorax_geometry(n_views: int) -> dict:
+    """256^3 at 1.05 mm; the scanner of Sec. 3.2: DSO 810 mm, DSD 1195 mm, 512 x
+    364 detector at 0.776 mm."""
+    return dict(nx=256, ny=256, nz=256, vx=1.05, vy=1.05, vz=1.05, nu=512, nv=364,
+                du=0.776, dv=0.776, dso=810.0, dsd=1195.0, n_views=n_views)
+
+
+def thorax_case(seed: int = 32):
+    """(prior, current): body, two lungs, spine and seeded nodules; the current
+    scan adds a needle (radius 1 voxel, length 60 voxels, value 2.0) in a lung."""
+    rng = np.random.default_rng(seed)
+    n = 256
+    vol = np.zeros((n, n, n))
+    c = np.array([128.0, 128.0, 128.0])
+    add_ellipsoid(vol, c, (118.0, 88.0, 400.0), np.eye(3), 1.0)           # body (all z)
+    for sx in (-1, 1):                                                     # lungs
+        add_ellipsoid(vol, c + [sx * 48.0, -8.0, 0.0], (36.0, 52.0, 100.0), np.eye(3), -0.75)
+    add_ellipsoid(vol, c + [0.0, 66.0, 0.0], (14.0, 14.0, 400.0), np.eye(3), 0.8)  # spine
+    for _ in range(10):                                                    # nodules, vessels
+        sx = rng.choice([-1, 1])
+        cc = c + [sx * 48.0, -8.0, 0.0] + rng.uniform(-25, 25, size=3)
+        add_ellipsoid(vol, cc, rng.uniform(2.0, 7.0, size=3), _rotation(rng), 0.7)
+    cur = vol.copy()
+    axis = random_unit(rng)
+    add_cylinder(cur, c + [-48.0, -8.0, 0.0], axis, 1.0, 60.0, 2.0)
+    return vol, cur
