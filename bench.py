@@ -287,10 +287,12 @@ def quality_bench(args, cbct, synth, np, torch, dev):
                 rows.append({"method": label, "iterations": iters, "time_s": round(sec, 4),
                              "psnr": round(metrics.psnr(xh, truth), 3),
                              "ssim": round(metrics.ssim(xh, truth), 4),
-                             "rel_l2": round(metrics.rel_l2(xh, truth), 5)})
+                             "rel_l2": round(metrics.rel_l2(xh, truth), 5),
+                             "change_err": round(metrics.change_recovery(xh, truth, prior), 4)})
                 log(f"[quality] {name} {V} views {label:10s} {iters:>14s}: PSNR "
                     f"{rows[-1]['psnr']:.2f} SSIM {rows[-1]['ssim']:.4f} "
-                    f"rel {rows[-1]['rel_l2']:.4f} ({sec * 1e3:.0f} ms)")
+                    f"rel {rows[-1]['rel_l2']:.4f} change {rows[-1]['change_err']:.3f} "
+                    f"({sec * 1e3:.0f} ms)")
 
             def timed(fn):
                 torch.cuda.synchronize()

@@ -355,7 +355,7 @@ void launch_forward(const GeoK &G, int mode, const FwdArgs &a, hipStream_t s, in
 // some a' in [aa, ab], a range of at most C rows (C computed on the host from the
 // geometry).  Each candidate row's chord is the overlap of [aa, ab] with the
 // cell's own z-plane interval,
-//     c = max(0, min(ab, max(zA, zB)) - max(aa, min(zA, zB))),
+//     c = med3(ab, zA, zB) - med3(aa, zA, zB)   (med3 = clamp into [min, max]),
 // zA, zB = fma(k, rg, cz), fma(k + 1, rg, cz).  Because the forward kernel's cell
 // state satisfies entry(k) < aa <= exit(k) at every segment start and meets at
 // most one z plane per segment, this equals its c0 / c1 bit for bit and is 0 for
@@ -471,10 +471,11 @@ k_back(GeoK G, const float *__restrict__ yhat, float *__restrict__ out, const in
                     const float zB = plane_alpha(fk1[q], z.x, z.y);
                     // med3(t, zA, zB) clamps t into the cell's interval: where the two
                     // intervals overlap these are max(aa, zmin) and min(ab, zmax), and
-                    // where they do not the difference is <= 0 either way
+                    // where they do not both clamp to the same end, giving 0.  The
+                    // clamp is non-decreasing in t and aa < ab, so hi - lo >= 0.
                     const float lo = __builtin_amdgcn_fmed3f(aa, zA, zB);
                     const float hi = __builtin_amdgcn_fmed3f(ab, zA, zB);
-                    a = fmaf(fmaxf(hi - lo, 0.0f), yq[c], a);
+                    a = fmaf(hi - lo, yq[c], a);
                 }
                 acc[q] = a;  // lanes past the column's end are never stored
             }

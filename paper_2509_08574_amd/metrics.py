@@ -38,3 +38,15 @@ def ssim(x, truth, sigma: float = 1.5) -> float:
     cxt = f(x * t) - mx * mt
     s = ((2 * mx * mt + c1) * (2 * cxt + c2)) / ((mx * mx + mt * mt + c1) * (vx + vt + c2))
     return float(s.mean())
+
+
+def change_recovery(x, truth, prior, dilate: int = 2) -> float:
+    """||x - truth|| / ||truth - prior|| over the voxels where truth and prior
+    differ, grown by `dilate` voxels: 1 when x shows none of the change (x =
+    prior there), 0 when it recovers it exactly."""
+    from scipy.ndimage import binary_dilation
+    t = np.asarray(truth, dtype=np.float64)
+    p = np.asarray(prior, dtype=np.float64)
+    m = binary_dilation(t != p, iterations=dilate)
+    d = np.linalg.norm((t - p)[m])
+    return float(np.linalg.norm((np.asarray(x, dtype=np.float64) - t)[m]) / d)

@@ -48,3 +48,14 @@ def test_ssim_of_a_scaled_image():
     mu = 0.5
     far = (2 * k * mu * mu + c1) / ((1 + k * k) * mu * mu + c1)
     assert abs(s - far) < 0.02
+
+
+def test_change_recovery_endpoints():
+    rng = np.random.default_rng(2)
+    prior = rng.uniform(size=(10, 10, 10))
+    truth = prior.copy()
+    truth[4:6, 4:6, 4:6] += 1.0
+    assert abs(metrics.change_recovery(prior, truth, prior) - 1.0) < 1e-12
+    assert metrics.change_recovery(truth, truth, prior) == 0.0
+    half = prior + 0.5 * (truth - prior)
+    assert abs(metrics.change_recovery(half, truth, prior) - 0.5) < 1e-12
