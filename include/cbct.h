@@ -169,7 +169,7 @@ int piccs_weights(const cbct_geom *g, const float *x, const float *xp, double ta
  *      the circle (2 pi / V for equal spacing).
  * Full 360-degree scans.  Device pointers; a temporary of (N + M) floats is
  * taken from the stream's memory pool.  Errors: CBCT_ERR_INVALID (null pointer,
- * nu > 1900), CBCT_ERR_OOM, CBCT_ERR_DEVICE.
+ * nu > 4680), CBCT_ERR_OOM, CBCT_ERR_DEVICE.
  */
 int cbct_fdk(const cbct_geom *g, const float *y, float *x, void *hip_stream);
 

@@ -4,56 +4,63 @@
 //   k_fdk_filter: each detector row is weighted by DSD / sqrt(DSD^2 + u^2 + v^2)
 //     and convolved along u with the band-limited ramp at the isocentre pitch
 //     dp = du DSO / DSD (taps 1/(4 dp^2) at 0, -1/(n pi dp)^2 at odd n, times
-//     dp).  A block stages a tile of rows in LDS; the result is written in the
-//     column layout [view][u][v] read by the backprojector.
+//     dp).  A block stages a tile of zero-padded rows in LDS; the result is
+//     written in the column layout [view][u][v] read by the backprojector.
 //   k_fdk_back: voxel-driven backprojection.  One wave per voxel column (i, j),
 //     lanes over its cells (as in the adjoint projector): per view, the depth U
 //     along the central ray and the detector column u are the same for the
 //     whole column, and v varies linearly with z.  Bilinear interpolation, zero
 //     outside the detector, weight (dbeta / 2) (DSO / U)^2.
+#include <algorithm>
+
 #include "chord.h"
 #include "internal.h"
 
 namespace cbct {
 
-constexpr int kFdkRows = 8;  // detector rows per filter block
-
+// Filter block: `rows` detector rows of one view in LDS, each stored with nu
+// zeros on both sides (the taps reach nu - 1 samples away, so the sums need no
+// bounds tests) at an odd stride (rows at the same u fall in different banks).
 __global__ void __launch_bounds__(256)
-k_fdk_filter(GeoK G, const float *__restrict__ y, float *__restrict__ q) {
+k_fdk_filter(GeoK G, const float *__restrict__ y, float *__restrict__ q, int rows) {
     extern __shared__ float lds[];
-    const int nu = G.nu, nh = nu / 2 + 1;
-    float *row = lds;                    // [kFdkRows][nu] weighted samples
-    float *tap = lds + kFdkRows * nu;    // [nh] ramp taps
-    const int nrt = (G.nv + kFdkRows - 1) / kFdkRows;
+    const int nu = G.nu, nh = nu / 2 + 1, S = 3 * nu + 1;
+    float *tap = lds;            // [nh] ramp taps
+    float *row = lds + nh;       // [rows][S]
+    const int nrt = (G.nv + rows - 1) / rows;
     const int view = blockIdx.x / nrt;
-    const int v0 = (blockIdx.x % nrt) * kFdkRows;
-    const int nr = min(kFdkRows, G.nv - v0);
+    const int v0 = (blockIdx.x % nrt) * rows;
+    const int nr = min(rows, G.nv - v0);
     for (int t = threadIdx.x; t < nh; t += blockDim.x) tap[t] = G.ramp[t];
-    for (int t = threadIdx.x; t < kFdkRows * nu; t += blockDim.x) {
-        const int r = t / nu, u = t % nu;
+    for (int t = threadIdx.x; t < rows * S; t += blockDim.x) {
+        const int r = t / S, e = t % S - nu;   // e: sample index, outside [0, nu) is padding
         float w = 0.0f;
-        if (r < nr) {
+        if (r < nr && e >= 0 && e < nu) {
             const int v = v0 + r;
-            const float L2 = G.Lu2[u] + G.Lv2[v];
-            w = y[((size_t)view * G.nv + v) * nu + u] * (G.dsd / sqrtf(L2));
+            const float L2 = G.Lu2[e] + G.Lv2[v];
+            w = y[((size_t)view * G.nv + v) * nu + e] * (G.dsd / sqrtf(L2));
         }
         row[t] = w;
     }
     __syncthreads();
     // output (u, r) with r fastest: consecutive threads write consecutive v
-    for (int t = threadIdx.x; t < kFdkRows * nu; t += blockDim.x) {
-        const int r = t % kFdkRows, u = t / kFdkRows;
+    for (int t = threadIdx.x; t < rows * nu; t += blockDim.x) {
+        const int r = t % rows, u = t / rows;
         if (r >= nr) continue;
-        const float *rw = row + r * nu;
-        float acc = tap[0] * rw[u];
+        const float *rw = row + r * S + nu + u;   // sample u
+        float acc = tap[0] * rw[0];
         for (int m = 0; 2 * m + 1 < nu; ++m) {
             const int n = 2 * m + 1;
-            const float a = u - n >= 0 ? rw[u - n] : 0.0f;
-            const float b = u + n < nu ? rw[u + n] : 0.0f;
-            acc = fmaf(tap[m + 1], a + b, acc);
+            acc = fmaf(tap[m + 1], rw[-n] + rw[n], acc);
         }
         q[((size_t)view * nu + u) * G.nv + v0 + r] = acc;
     }
+}
+
+// rows per filter block such that taps and padded rows fit in 64 KB of LDS
+static int fdk_rows(int nu) {
+    const int S = 3 * nu + 1, nh = nu / 2 + 1;
+    return std::max(0, std::min(8, (16384 - nh) / S));
 }
 
 __global__ void __launch_bounds__(256)
@@ -152,18 +159,19 @@ extern "C" int cbct_fdk(const cbct_geom *gc, const float *y, float *x, void *hip
         CBCT_REQUIRE(gc && y && x, "null argument");
         cbct_geom *g = const_cast<cbct_geom *>(gc);
         const int nu = g->d.nu;
-        const size_t lds = sizeof(float) * ((size_t)kFdkRows * nu + nu / 2 + 1);
-        CBCT_REQUIRE(lds <= 64 * 1024, "detector rows too long for the FDK filter (nu > 1900)");
+        const int rows = fdk_rows(nu);
+        CBCT_REQUIRE(rows >= 1, "detector rows too long for the FDK filter (nu > 4680)");
+        const size_t lds = sizeof(float) * ((size_t)rows * (3 * nu + 1) + nu / 2 + 1);
         const GeoK G = geo_for_device(g);
         const size_t nq_bytes = sizeof(float) * (size_t)g->n_proj();
         const size_t nv_bytes = sizeof(float) * (size_t)g->pad_floats();
         CBCT_HIP(hipMallocAsync(&tmp, nq_bytes + nv_bytes + 256, s));
         float *q = (float *)tmp;
         float *cols = (float *)((char *)tmp + ((nq_bytes + 255) & ~(size_t)255));
-        const int nrt = (G.nv + kFdkRows - 1) / kFdkRows;
+        const int nrt = (G.nv + rows - 1) / rows;
         const int64_t nbf = (int64_t)G.nviews * nrt;
         CBCT_REQUIRE(nbf <= 0x7fffffff, "FDK filter grid too large");
-        hipLaunchKernelGGL(k_fdk_filter, dim3((unsigned)nbf), dim3(256), lds, s, G, y, q);
+        hipLaunchKernelGGL(k_fdk_filter, dim3((unsigned)nbf), dim3(256), lds, s, G, y, q, rows);
         CBCT_HIP(hipGetLastError());
         const int nq = std::min(8, (G.nz + 63) / 64);
         const int kspan = 64 * nq;

@@ -130,7 +130,7 @@ def test_fdk_argument_checks(lib):
     g = lib.Geometry(**C1)
     so = lib._lib
     assert so.cbct_fdk(g.handle, None, None, None) == lib.ERR_INVALID
-    wide = lib.Geometry(**dict(C1, nu=2048, du=0.07))
+    wide = lib.Geometry(**dict(C1, nu=4800, du=0.03))
     assert so.cbct_fdk(wide.handle, ctypes.c_void_p(16), ctypes.c_void_p(16), None) == \
         lib.ERR_INVALID
     assert "too long" in lib.last_error()
