@@ -20,11 +20,17 @@ namespace cbct {
 
 // Filter block: `rows` detector rows of one view in LDS, each stored with nu
 // zeros on both sides (the taps reach nu - 1 samples away, so the sums need no
-// bounds tests) at an odd stride (rows at the same u fall in different banks).
+// bounds tests) at a stride of 4 mod 32 floats: the 8 rows x 4 consecutive u a
+// half-wave reads fall in 32 different banks.
+__host__ __device__ inline int fdk_stride(int nu) {
+    const int s = 3 * nu;
+    return s + ((4 - s % 32) + 32) % 32;
+}
+
 __global__ void __launch_bounds__(256)
 k_fdk_filter(GeoK G, const float *__restrict__ y, float *__restrict__ q, int rows) {
     extern __shared__ float lds[];
-    const int nu = G.nu, nh = nu / 2 + 1, S = 3 * nu + 1;
+    const int nu = G.nu, nh = nu / 2 + 1, S = fdk_stride(nu);
     float *tap = lds;            // [nh] ramp taps
     float *row = lds + nh;       // [rows][S]
     const int nrt = (G.nv + rows - 1) / rows;
@@ -43,23 +49,38 @@ k_fdk_filter(GeoK G, const float *__restrict__ y, float *__restrict__ q, int row
         row[t] = w;
     }
     __syncthreads();
-    // output (u, r) with r fastest: consecutive threads write consecutive v
-    for (int t = threadIdx.x; t < rows * nu; t += blockDim.x) {
-        const int r = t % rows, u = t / rows;
-        if (r >= nr) continue;
-        const float *rw = row + r * S + nu + u;   // sample u
-        float acc = tap[0] * rw[0];
+    // outputs t = (u, r) with r fastest (consecutive threads write consecutive
+    // v); each thread keeps up to kOut outputs in registers and walks the taps
+    // once for all of them
+    constexpr int kOut = 16;
+    const int nout = rows * nu;
+    for (int base = 0; base < nout; base += kOut * 256) {
+        const float *rw[kOut];
+        float acc[kOut];
+#pragma unroll
+        for (int j = 0; j < kOut; ++j) {
+            const int t = min(base + (int)threadIdx.x + 256 * j, nout - 1);
+            rw[j] = row + (t % rows) * S + nu + t / rows;   // sample u of row r
+            acc[j] = tap[0] * rw[j][0];
+        }
         for (int m = 0; 2 * m + 1 < nu; ++m) {
             const int n = 2 * m + 1;
-            acc = fmaf(tap[m + 1], rw[-n] + rw[n], acc);
+            const float h = tap[m + 1];
+#pragma unroll
+            for (int j = 0; j < kOut; ++j) acc[j] = fmaf(h, rw[j][-n] + rw[j][n], acc[j]);
         }
-        q[((size_t)view * nu + u) * G.nv + v0 + r] = acc;
+#pragma unroll
+        for (int j = 0; j < kOut; ++j) {
+            const int t = base + (int)threadIdx.x + 256 * j;
+            const int r = t % rows, u = t / rows;
+            if (t < nout && r < nr) q[((size_t)view * nu + u) * G.nv + v0 + r] = acc[j];
+        }
     }
 }
 
 // rows per filter block such that taps and padded rows fit in 64 KB of LDS
 static int fdk_rows(int nu) {
-    const int S = 3 * nu + 1, nh = nu / 2 + 1;
+    const int S = fdk_stride(nu), nh = nu / 2 + 1;
     return std::max(0, std::min(8, (16384 - nh) / S));
 }
 
@@ -161,7 +182,7 @@ extern "C" int cbct_fdk(const cbct_geom *gc, const float *y, float *x, void *hip
         const int nu = g->d.nu;
         const int rows = fdk_rows(nu);
         CBCT_REQUIRE(rows >= 1, "detector rows too long for the FDK filter (nu > 4680)");
-        const size_t lds = sizeof(float) * ((size_t)rows * (3 * nu + 1) + nu / 2 + 1);
+        const size_t lds = sizeof(float) * ((size_t)rows * fdk_stride(nu) + nu / 2 + 1);
         const GeoK G = geo_for_device(g);
         const size_t nq_bytes = sizeof(float) * (size_t)g->n_proj();
         const size_t nv_bytes = sizeof(float) * (size_t)g->pad_floats();
