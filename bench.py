@@ -46,10 +46,11 @@ def kernel_source_hash():
     return h.hexdigest()
 
 
-def recorded_traffic(kernel, workload):
-    """HBM bytes per launch from the committed rocprofv3 summary of `kernel` on
-    `workload` (FETCH_SIZE + WRITE_SIZE, calibrated), or None if there is none
-    or the kernel sources changed since it was taken."""
+def recorded_profile(kernel, workload, key):
+    """A per-launch figure (`traffic_bytes_per_launch`: FETCH_SIZE + WRITE_SIZE,
+    calibrated; `valu_wave_instructions_per_launch`: SQ_INSTS_VALU) from the
+    committed rocprofv3 summary of `kernel` on `workload`, or None if there is
+    none or the kernel sources changed since it was taken."""
     path = os.path.join(PROFILES, f"{kernel}_{workload}.md")
     if not os.path.exists(path):
         return None
@@ -62,9 +63,17 @@ def recorded_traffic(kernel, workload):
     if rec.get("kernel_source_sha256") != kernel_source_hash():
         return None
     try:
-        return float(rec["traffic_bytes_per_launch"])
+        return float(rec[key])
     except (KeyError, ValueError):
         return None
+
+
+def recorded_traffic(kernel, workload):
+    return recorded_profile(kernel, workload, "traffic_bytes_per_launch")
+
+
+# One wave64 FP32 VALU instruction per SIMD per 4 cycles: 256 CUs x 4 SIMDs x 2.4 GHz / 4.
+VALU_PEAK_WAVE_INSTR_S = 256 * 4 * 2.4e9 / 4
 
 
 def projector_roofline(args, cbct, torch, g, xc, ywc, stream):
@@ -104,6 +113,16 @@ def projector_roofline(args, cbct, torch, g, xc, ywc, stream):
                 "algorithmic_bytes_per_launch": dom[2], "units_per_launch": nnz,
                 "unit_bytes": "4 B per chord + 4 B per output element",
                 "traffic_source": f"profiles/{dom[0]}_{args.workload}.md" if traffic else None}
+    valu = recorded_profile(dom[0], args.workload, "valu_wave_instructions_per_launch")
+    if valu:
+        # what binds the projectors: VALU issue (recorded instruction count over
+        # this run's launch time, against the nominal issue peak)
+        rate = valu / (dom[1] * 1e-3)
+        roofline["valu"] = {"bound": "alu", "achieved": round(rate / 1e9, 1),
+                            "peak": VALU_PEAK_WAVE_INSTR_S / 1e9,
+                            "unit": "G wave-instructions/s",
+                            "frac": round(rate / VALU_PEAK_WAVE_INSTR_S, 4),
+                            "instructions_per_launch": valu}
     return t_fwd, t_back, nnz, gvp_fwd, gvp_back, roofline
 
 
