@@ -343,6 +343,103 @@ def quality_bench(args, cbct, synth, np, torch, dev):
     return out
 
 
+def c3_precision_bench(args, cbct, synth, np, torch, dev):
+    """512^3 / 120 views / 1024 x 768: FP32 vs mixed BF16 vs mixed FP16 solves
+    (5 x 10), prior = the object without the change, I0 = 5e4."""
+    gd = synth.geometry("c3_512")
+    sp = synth.SOLVE_PARAMS["c2"]
+    t = time.time()
+    prior, cur = synth.c3_case()
+    log(f"[c3] phantom 512^3 in {time.time() - t:.1f}s")
+    g = cbct.Geometry.from_dict(gd)
+    xp = torch.from_numpy(prior.astype(np.float32)).to(dev)
+    tr = torch.from_numpy(cur.astype(np.float32)).to(dev)
+    del prior, cur
+    y = cbct.forward(g, tr)
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(3)
+    lam = sp["I0"] * torch.exp(-synth.MU_WATER_PER_MM * y.double())
+    b = (-torch.log(torch.clamp(torch.poisson(lam, generator=gen), min=1.0) / sp["I0"])
+         / synth.MU_WATER_PER_MM).float()
+    del lam, y
+    out, ref = {}, None
+    for name, pr in (("fp32", cbct.PREC_FP32), ("mixed_bf16", cbct.PREC_MIXED_BF16),
+                     ("mixed_f16", cbct.PREC_MIXED_F16)):
+        p = cbct.SolveParams(sp["alpha"], sp["lam"], sp["tau"], sp["n_outer"], sp["n_inner"],
+                             precision=pr)
+        ws = cbct.alloc_workspace(g, p, device=dev)
+        x = xp.clone()
+        cbct.solve(g, b, xp, x, p, workspace=ws, report=False)   # warm-up
+        torch.cuda.synchronize()
+        reps = 2
+        t = time.perf_counter()
+        for _ in range(reps):
+            x.copy_(xp)
+            cbct.solve(g, b, xp, x, p, workspace=ws, report=False)
+        torch.cuda.synchronize()
+        sec = (time.perf_counter() - t) / reps
+        if ref is None:
+            ref = x.clone()
+        out[name] = {"s_per_recon": round(sec, 3),
+                     "rel_err_vs_truth": round(float(torch.linalg.norm(x - tr)
+                                                     / torch.linalg.norm(tr)), 5),
+                     "rel_l2_vs_fp32": float(torch.linalg.norm(x - ref) / torch.linalg.norm(ref))}
+        del ws
+        log(f"[c3] {name}: {sec:.3f} s/recon, err vs truth {out[name]['rel_err_vs_truth']}")
+    for k in out:
+        out[k]["speedup_vs_fp32"] = round(out["fp32"]["s_per_recon"] / out[k]["s_per_recon"], 3)
+    out["prior_rel_err_vs_truth"] = round(float(torch.linalg.norm(xp - tr)
+                                                / torch.linalg.norm(tr)), 5)
+    return out
+
+
+def c5_repeated_bench(args, cbct, synth, np, torch, dev):
+    """Ten 180-view scans of 512 x 512 x 400 with a needle advancing 3 mm per
+    scan, served for one patient: x_p = anatomy without the needle resident on
+    the device, each scan warm-started from the previous reconstruction
+    (device-resident), 4 x 10 iterations.  FP32, then mixed BF16."""
+    gd = synth.geometry("c5")
+    sp = synth.SOLVE_PARAMS["c5"]
+    t = time.time()
+    base, centre, axis = synth.c5_case()
+    log(f"[c5] phantom 512x512x400 in {time.time() - t:.1f}s")
+    g = cbct.Geometry.from_dict(gd)
+    base_d = torch.from_numpy(base.astype(np.float32)).to(dev)
+    gen = torch.Generator(device=dev)
+    scans = []
+    for s_ in range(1, 11):
+        cur = base_d.clone()
+        cur.view(-1)[torch.from_numpy(synth.c5_scan(base, centre, axis, s_)).to(dev)] = 2.0
+        y = cbct.forward(g, cur)
+        gen.manual_seed(500 + s_)
+        lam = sp["I0"] * torch.exp(-synth.MU_WATER_PER_MM * y.double())
+        b = (-torch.log(torch.clamp(torch.poisson(lam, generator=gen), min=1.0) / sp["I0"])
+             / synth.MU_WATER_PER_MM).float().cpu().numpy()
+        scans.append((b, cur.cpu().numpy()))
+        del y, lam, cur
+    g.close()
+    log(f"[c5] 10 scans ready ({time.time() - t:.1f}s)")
+    out = {}
+    for name, pr in (("fp32", cbct.PREC_FP32), ("mixed_bf16", cbct.PREC_MIXED_BF16)):
+        p = cbct.SolveParams(sp["alpha"], sp["lam"], sp["tau"], sp["n_outer"], sp["n_inner"],
+                             precision=pr)
+        rows = []
+        with cbct.Server(hbm_budget_bytes=32 << 30, max_slots=1) as srv:
+            srv.add_prior(0, gd, base.astype(np.float32))
+            xo = np.empty(base.shape, np.float32)
+            for s_, (b, truth) in enumerate(scans, 1):
+                tk = srv.submit(0, gd, b, p, cbct.X0_PREVIOUS)
+                rc, _, info = srv.wait(tk, xo, timeout=600)
+                assert rc == 0, info["error"]
+                err = float(np.linalg.norm(xo - truth) / np.linalg.norm(truth))
+                rows.append({"scan": s_, "latency_s": round(info["t_done"] - info["t_submit"], 3),
+                             "gpu_s": round(info["t_done"] - info["t_admit"], 3),
+                             "rel_err_vs_truth": round(err, 5)})
+                log(f"[c5] {name} scan {s_}: {rows[-1]['latency_s']:.2f} s, err {err:.4f}")
+        out[name] = rows
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -360,6 +457,10 @@ def main():
     ap.add_argument("--quality", action="store_true",
                     help="only the head / thorax stand-in quality table (PSNR, SSIM)")
     ap.add_argument("--quality-head-only", action="store_true")
+    ap.add_argument("--c3-precision", action="store_true",
+                    help="only the 512^3 / 120-view FP32 vs mixed comparison")
+    ap.add_argument("--c5-repeated", action="store_true",
+                    help="only the ten-scan 512x512x400 repeated sequence through the server")
     ap.add_argument("--ops-only", action="store_true",
                     help="time only the projector pair on random data (profiler passes)")
     ap.add_argument("--serve-only", action="store_true",
@@ -409,6 +510,14 @@ def main():
         return
     if args.serve_only:
         print(json.dumps({"serving": serving_bench(args, cbct, synth, np, torch, dev)}),
+              flush=True)
+        return
+    if args.c3_precision:
+        print(json.dumps({"c3_precision": c3_precision_bench(args, cbct, synth, np, torch, dev)}),
+              flush=True)
+        return
+    if args.c5_repeated:
+        print(json.dumps({"c5_repeated": c5_repeated_bench(args, cbct, synth, np, torch, dev)}),
               flush=True)
         return
     if args.quality:

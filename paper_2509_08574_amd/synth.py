@@ -41,12 +41,15 @@ def _grid(shape):
     return (np.arange(nz) + 0.5, np.arange(ny) + 0.5, np.arange(nx) + 0.5)
 
 
-def add_ellipsoid(vol: np.ndarray, centre, semi, R, value, mode="add"):
-    """Voxel-centre voxelisation of {p : |R^T (p - c) / a| <= 1} (voxel units, (x,y,z))."""
+def add_ellipsoid(vol: np.ndarray, centre, semi, R, value, mode="add", zrange=None):
+    """Voxel-centre voxelisation of {p : |R^T (p - c) / a| <= 1} (voxel units, (x,y,z)),
+    optionally restricted to the z planes zrange = (z0, z1)."""
     nz, ny, nx = vol.shape
     rmax = float(max(semi))
     lo = [max(0, int(math.floor(centre[a] - rmax)) - 1) for a in range(3)]
     hi = [min(n, int(math.ceil(centre[a] + rmax)) + 1) for a, n in enumerate((nx, ny, nz))]
+    if zrange is not None:
+        lo[2], hi[2] = max(lo[2], zrange[0]), min(hi[2], zrange[1])
     if any(h <= l for l, h in zip(lo, hi)):
         return
     yc = (np.arange(lo[1], hi[1]) + 0.5 - centre[1])[None, :, None]
@@ -92,8 +95,12 @@ def add_cylinder(vol: np.ndarray, centre, axis, radius, length, value):
     vol.reshape(-1)[cylinder_indices(vol.shape, centre, axis, radius, length)] = value
 
 
-def ellipsoid_phantom(shape, n_ell, semi_range, seed, dens_range=(0.1, 1.0)):
-    """Sum of ``n_ell`` random ellipsoids; returns (volume, list of ellipsoid params)."""
+def ellipsoid_phantom(shape, n_ell, semi_range, seed, dens_range=(0.1, 1.0), threads=1):
+    """Sum of ``n_ell`` random ellipsoids; returns (volume, list of ellipsoid params).
+
+    With threads > 1 the volume is filled by z slabs in parallel; every voxel
+    receives the same additions in the same order, so the result is identical.
+    """
     rng = np.random.default_rng(seed)
     nz, ny, nx = shape
     vol = np.zeros(shape, dtype=np.float64)
@@ -104,7 +111,18 @@ def ellipsoid_phantom(shape, n_ell, semi_range, seed, dens_range=(0.1, 1.0)):
         R = _rotation(rng)
         rho = rng.uniform(*dens_range)
         ells.append((c, a, R, rho))
-        add_ellipsoid(vol, c, a, R, rho)
+
+    def fill(z0, z1):
+        for c, a, R, rho in ells:
+            add_ellipsoid(vol, c, a, R, rho, zrange=(z0, z1))
+
+    if threads <= 1:
+        fill(0, nz)
+    else:
+        from concurrent.futures import ThreadPoolExecutor
+        step = -(-nz // (4 * threads))
+        with ThreadPoolExecutor(threads) as ex:
+            list(ex.map(lambda z: fill(z, min(z + step, nz)), range(0, nz, step)))
     return vol, ells
 
 
@@ -303,3 +321,42 @@ def thorax_case(seed: int = 32):
     axis = random_unit(rng)
     add_cylinder(cur, c + [-48.0, -8.0, 0.0], axis, 1.0, 60.0, 2.0)
     return vol, cur
+
+
+# --------------------------------------------------------------------------
+# Large cases: the 512^3 precision comparison and the repeated-scan sequence.
+
+def c3_case(seed: int = 3):
+    """512^3 at 0.5 mm: the 256^3 object family at twice the resolution
+    (30 ellipsoids, semi-axes U[32, 192] voxels, scaled to a peak of 1), the
+    smallest one grown by 1.3.  Returns (prior = object without the change,
+    current)."""
+    shape = (512, 512, 512)
+    base, ells = ellipsoid_phantom(shape, 30, (32.0, 192.0), seed, threads=8)
+    k = int(np.argmin([np.prod(a) for (_, a, _, _) in ells]))
+    c, a, R, rho = ells[k]
+    cur = base.copy()
+    add_ellipsoid(cur, c, a, R, -rho)
+    add_ellipsoid(cur, c, 1.3 * a, R, rho)
+    scale = 1.0 / base.max()
+    return base * scale, cur * scale
+
+
+def c5_case(seed: int = 5):
+    """512 x 512 x 400 at 0.4 mm: 30 ellipsoids (semi-axes U[32, 192] voxels)
+    scaled to a peak of 1, and a needle (radius 2.5 voxels, length 100 voxels,
+    value 2.0) at a seeded position and direction.  Returns (anatomy, needle
+    centre, needle axis); scan s (1..10) has the needle advanced by 7.5 (s - 1)
+    voxels along its axis (3 mm per scan)."""
+    rng = np.random.default_rng(seed + 100)
+    shape = (400, 512, 512)
+    base, _ = ellipsoid_phantom(shape, 30, (32.0, 192.0), seed, threads=8)
+    base *= 1.0 / base.max()
+    centre = np.array([rng.uniform(0.35 * n, 0.55 * n) for n in (512, 512, 400)])
+    axis = random_unit(rng)
+    return base, centre, axis
+
+
+def c5_scan(base, centre, axis, scan: int) -> np.ndarray:
+    """Flat voxel indices of the needle in scan `scan` (1-based)."""
+    return cylinder_indices(base.shape, centre + 7.5 * (scan - 1) * axis, axis, 2.5, 100.0)
