@@ -13,25 +13,36 @@ void set_last_error(const std::string &msg) { g_last_error = msg; }
 void clear_last_error() { g_last_error.clear(); }
 
 // Coefficients of one axis of a ray written as
-//   index position(a') = c0 + a' * dpos,  a' = alpha - a_ref,
+//   index position(a') = o + c0 + a' * dpos,  a' = alpha - a_ref,  o = n / 2,
 // from the source coordinate S, direction component d (P - S) and the grid's
-// low edge lo and cell size h.  Plane p is crossed at a' = (p - c0) / dpos,
-// evaluated by the kernels as fma(p, r, c) with r = 1/dpos and c = -c0/dpos
-// rounded once from float64.
-static void axis_coeffs(double S, double d, double lo, double h, double a_ref, float &c0,
-                        float &r, float &c, float &dpos_f) {
+// low edge lo, cell size h and cell count n.  Plane p is crossed at
+// a' = (p - o - c0) / dpos, evaluated by the kernels as fma(p - o, r, c) with
+// r = 1/dpos rounded to float and c = -c0 * r rounded once from float64.
+// Counting planes from the middle of the axis and deriving c from the rounded
+// r keeps the float32 cancellation in that fma to the ray's distance from the
+// axis midpoint: a crossing is off by about eps * |p - o| cells rather than
+// eps * p, and a rounding of r only scales the ray about its own a' = 0.
+static void axis_coeffs(double S, double d, double lo, double h, int n, double a_ref,
+                        float &c0, float &r, float &c, float &dpos_f) {
     const double dpos = d / h;                     // index units per unit alpha
     const double pos_ref = (S - lo) / h + a_ref * dpos;  // index position at a' = 0
-    c0 = (float)pos_ref;
+    const int o = n >> 1;
+    const double rel = pos_ref - o;
+    c0 = (float)rel;
     dpos_f = (float)dpos;
     if (std::fabs(dpos) > 1e-30) {
         r = (float)(1.0 / dpos);
-        c = (float)(-pos_ref / dpos);
+        c = (float)(-rel * (double)r);
     } else {
-        // A ray parallel to the planes never crosses them: a huge finite slope
-        // keeps the plane parameters finite and far outside any interval.
+        // A ray parallel to the planes never crosses them.  Its cell is
+        // floor(pos) inside the box (a ray lying in an interior plane belongs to
+        // the cell above it, as with Siddon's midpoint rule) and none when it
+        // lies in or beyond an outer face (cell -1 or n).  Planes at or below
+        // that cell get parameter -huge, the others +huge: half a plane spacing
+        // times 1e30, so float rounding cannot move a plane to the wrong side.
+        const double kc = pos_ref <= 0.0 ? -1.0 : (pos_ref >= n ? (double)n : std::floor(pos_ref));
         r = 1e30f;
-        c = (float)(-pos_ref * 1e30);
+        c = (float)(-(kc - o + 0.5) * 1e30);
     }
 }
 
@@ -52,8 +63,8 @@ static void build_tables(cbct_geom *g) {
             const double Px = (d.dso - d.dsd) * c - u * s;
             const double Py = (d.dso - d.dsd) * s + u * c;
             float xi0, rx, cx, dx, eta0, ry, cy, dy;
-            axis_coeffs(Sx, Px - Sx, xlo, d.vx, a_ref, xi0, rx, cx, dx);
-            axis_coeffs(Sy, Py - Sy, ylo, d.vy, a_ref, eta0, ry, cy, dy);
+            axis_coeffs(Sx, Px - Sx, xlo, d.vx, d.nx, a_ref, xi0, rx, cx, dx);
+            axis_coeffs(Sy, Py - Sy, ylo, d.vy, d.ny, a_ref, eta0, ry, cy, dy);
             g->xy[(size_t)v * d.nu + iu] = make_float4(rx, cx, ry, cy);
             g->xy0[(size_t)v * d.nu + iu] = make_float2(xi0, eta0);
         }
@@ -63,7 +74,7 @@ static void build_tables(cbct_geom *g) {
     for (int iv = 0; iv < d.nv; ++iv) {
         const double vmm = (iv + 0.5) * d.dv - d.nv * d.dv / 2.0;
         float z0, rg, cz, dz;
-        axis_coeffs(0.0, vmm, zlo, d.vz, a_ref, z0, rg, cz, dz);
+        axis_coeffs(0.0, vmm, zlo, d.vz, d.nz, a_ref, z0, rg, cz, dz);
         g->zr[(size_t)iv] = make_float4(z0, rg, cz, dz);
         g->Lv2[(size_t)iv] = (float)(vmm * vmm);
     }

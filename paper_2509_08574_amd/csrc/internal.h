@@ -52,9 +52,10 @@ struct GeoK {
     int Z;               // nz + 2
     float hx, hy, hz;    // voxel size [mm] (detector footprints and row ranges only)
     float dso, dsd, du, dv;
-    const float4 *xy;    // [nviews*nu]: (rx, cx, ry, cy): x plane p at a' = fma(p, rx, cx)
-    const float2 *xy0;   // [nviews*nu]: (xi0, eta0): x, y index positions at a' = 0
-    const float4 *zr;    // [nv]: (z0, rg, cz, dz): z plane p at a' = fma(p, rg, cz)
+    // plane indices p enter as p - n/2 (n = nx, ny or nz, integer division)
+    const float4 *xy;    // [nviews*nu]: (rx, cx, ry, cy): x plane p at a' = fma(p - nx/2, rx, cx)
+    const float2 *xy0;   // [nviews*nu]: (xi0, eta0): x, y index positions at a' = 0, less n/2
+    const float4 *zr;    // [nv]: (z0, rg, cz, dz): z plane p at a' = fma(p - nz/2, rg, cz)
     const float *Lu2;    // [nu]: dsd^2 + u^2
     const float *Lv2;    // [nv]: v^2
     const float2 *trig;  // [nviews]: (cos th, sin th)

@@ -38,8 +38,12 @@ k_segtab(GeoK G, int2 *__restrict__ seghdr, int2 *__restrict__ seg) {
     if (r >= G.nviews * G.nu) return;
     const float4 cxy = G.xy[r];    // (rx, cx, ry, cy)
     const float2 c0 = G.xy0[r];    // (xi0, eta0)
-    const float ax0 = plane_alpha(0.0f, cxy.x, cxy.y), axN = plane_alpha((float)G.nx, cxy.x, cxy.y);
-    const float ay0 = plane_alpha(0.0f, cxy.z, cxy.w), ayN = plane_alpha((float)G.ny, cxy.z, cxy.w);
+    // plane indices relative to the axis midpoints
+    const int ox = G.nx >> 1, oy = G.ny >> 1;
+    const float ax0 = plane_alpha((float)(-ox), cxy.x, cxy.y);
+    const float axN = plane_alpha((float)(G.nx - ox), cxy.x, cxy.y);
+    const float ay0 = plane_alpha((float)(-oy), cxy.z, cxy.w);
+    const float ayN = plane_alpha((float)(G.ny - oy), cxy.z, cxy.w);
     const float a_in = fmaxf(fminf(ax0, axN), fminf(ay0, ayN));
     const float a_out = fminf(fmaxf(ax0, axN), fmaxf(ay0, ayN));
     int2 *out = seg + (size_t)r * G.seg_stride;
@@ -48,8 +52,8 @@ k_segtab(GeoK G, int2 *__restrict__ seghdr, int2 *__restrict__ seg) {
         const int sx = cxy.x > 0.0f ? 1 : -1, sy = cxy.z > 0.0f ? 1 : -1;
         int i = xy_cell(a_in, c0.x, cxy.x, cxy.y, G.nx);
         int j = xy_cell(a_in, c0.y, cxy.z, cxy.w, G.ny);
-        float axn = plane_alpha((float)(i + (sx > 0)), cxy.x, cxy.y);
-        float ayn = plane_alpha((float)(j + (sy > 0)), cxy.z, cxy.w);
+        float axn = plane_alpha((float)(i - ox + (sx > 0)), cxy.x, cxy.y);
+        float ayn = plane_alpha((float)(j - oy + (sy > 0)), cxy.z, cxy.w);
         const int nmax = G.seg_stride - kSegPad;
         while (n < nmax) {
             const float ab = fminf(axn, ayn);
@@ -57,11 +61,11 @@ k_segtab(GeoK G, int2 *__restrict__ seghdr, int2 *__restrict__ seg) {
             const bool adx = axn == ab, ady = ayn == ab;
             if (adx) {
                 i += sx;
-                axn = plane_alpha((float)(i + (sx > 0)), cxy.x, cxy.y);
+                axn = plane_alpha((float)(i - ox + (sx > 0)), cxy.x, cxy.y);
             }
             if (ady) {
                 j += sy;
-                ayn = plane_alpha((float)(j + (sy > 0)), cxy.z, cxy.w);
+                ayn = plane_alpha((float)(j - oy + (sy > 0)), cxy.z, cxy.w);
             }
             if ((unsigned)i >= (unsigned)G.nx || (unsigned)j >= (unsigned)G.ny) break;
         }
@@ -356,7 +360,7 @@ void launch_forward(const GeoK &G, int mode, const FwdArgs &a, hipStream_t s, in
 // geometry).  Each candidate row's chord is the overlap of [aa, ab] with the
 // cell's own z-plane interval,
 //     c = med3(ab, zA, zB) - med3(aa, zA, zB)   (med3 = clamp into [min, max]),
-// zA, zB = fma(k, rg, cz), fma(k + 1, rg, cz).  Because the forward kernel's cell
+// zA, zB = fma(k - o, rg, cz), fma(k + 1 - o, rg, cz), o = nz / 2.  Because the forward kernel's cell
 // state satisfies entry(k) < aa <= exit(k) at every segment start and meets at
 // most one z plane per segment, this equals its c0 / c1 bit for bit and is 0 for
 // every cell the forward does not touch: the two kernels apply the same matrix.
@@ -408,11 +412,13 @@ k_back(GeoK G, const float *__restrict__ yhat, float *__restrict__ out, const in
         acc[q] = 0.0f;
         const int k = kbase + lane + 64 * q;
         kok[q] = q < nq && k < G.nz;
-        fk[q] = (float)k;
+        fk[q] = (float)(k - (G.nz >> 1));      // plane index relative to nz / 2
         fk1[q] = fk[q] + 1.0f;
-        zk0[q] = fmaf(fk[q], G.hz, z_lo_mm);   // cell's lower z [mm]
+        zk0[q] = fmaf((float)k, G.hz, z_lo_mm);   // cell's lower z [mm]
     }
     const float fi = (float)i, fj = (float)j;
+    // the column's lower plane indices relative to the axis midpoints
+    const float px = (float)(i - (G.nx >> 1)), py = (float)(j - (G.ny >> 1));
     const float xlo = (fi - 0.5f * G.nx) * G.hx, xhi = xlo + G.hx;
     const float ylo = (fj - 0.5f * G.ny) * G.hy, yhi = ylo + G.hy;
     const float fu_scale = G.dsd / G.du, fu_off = 0.5f * G.nu - 0.5f;
@@ -442,10 +448,10 @@ k_back(GeoK G, const float *__restrict__ yhat, float *__restrict__ out, const in
             __builtin_amdgcn_readfirstlane(min(G.nu - 1, (int)floorf(umax + 1e-3f)));
         for (int iu = iu0; iu <= iu1; ++iu) {
             const float4 cxy = G.xy[(size_t)view * G.nu + iu];
-            const float ex0 = plane_alpha(fi, cxy.x, cxy.y);
-            const float ex1 = plane_alpha(fi + 1.0f, cxy.x, cxy.y);
-            const float ey0 = plane_alpha(fj, cxy.z, cxy.w);
-            const float ey1 = plane_alpha(fj + 1.0f, cxy.z, cxy.w);
+            const float ex0 = plane_alpha(px, cxy.x, cxy.y);
+            const float ex1 = plane_alpha(px + 1.0f, cxy.x, cxy.y);
+            const float ey0 = plane_alpha(py, cxy.z, cxy.w);
+            const float ey1 = plane_alpha(py + 1.0f, cxy.z, cxy.w);
             const float aa = fmaxf(fminf(ex0, ex1), fminf(ey0, ey1));
             const float ab = fminf(fmaxf(ex0, ex1), fmaxf(ey0, ey1));
             if (!(ab > aa)) continue;

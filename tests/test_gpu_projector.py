@@ -45,6 +45,24 @@ GEOMS = {
     # several 64-row blocks and a ragged tail; non-uniform angles
     "rows": dict(nx=20, ny=18, nz=24, vx=0.8, vy=0.8, vz=0.8, nu=30, nv=150, du=0.9, dv=0.3,
                  dso=60.0, dsd=100.0, n_views=9),
+    # degenerate sizes: one view, one detector row, one detector column, one
+    # voxel column along x
+    "one_view": dict(nx=9, ny=8, nz=6, vx=1.0, vy=1.0, vz=1.0, nu=12, nv=10, du=1.2, dv=1.2,
+                     dso=40.0, dsd=70.0, n_views=1),
+    "one_row": dict(nx=10, ny=9, nz=5, vx=1.0, vy=1.0, vz=1.0, nu=14, nv=1, du=1.2, dv=1.0,
+                    dso=40.0, dsd=70.0, n_views=6),
+    # (one detector column puts its only ray through the isocentre: odd nx, ny
+    # and no axis-aligned view keep it off the x and y planes, where a ray
+    # tilted only by the rounding of cos(pi/2) has no well-defined column.  The
+    # central detector row's rays are exactly parallel to z and, nz being even,
+    # lie in the plane z = 0: they belong to the cell above, as in the oracle.)
+    "one_col": dict(nx=7, ny=7, nz=6, vx=1.0, vy=1.0, vz=1.0, nu=1, nv=9, du=1.0, dv=1.2,
+                    dso=40.0, dsd=70.0, n_views=7),
+    "thin_x": dict(nx=1, ny=9, nz=7, vx=1.0, vy=1.0, vz=1.0, nu=13, nv=11, du=1.1, dv=1.1,
+                   dso=40.0, dsd=70.0, n_views=7),
+    # columns taller than 512 cells: the adjoint splits each column over waves
+    "tall": dict(nx=6, ny=5, nz=600, vx=0.2, vy=0.2, vz=0.2, nu=10, nv=300, du=0.4, dv=0.4,
+                 dso=70.0, dsd=110.0, n_views=5),
 }
 
 
@@ -71,7 +89,7 @@ def test_forward_and_back_match_oracle(orc, lib, name):
     assert np.all(yg[yo == 0] == 0)
 
 
-@pytest.mark.parametrize("name", ["odd", "slab"])
+@pytest.mark.parametrize("name", ["odd", "slab", "one_view", "one_row", "one_col", "thin_x"])
 def test_gpu_pair_is_exact_transpose(orc, lib, name):
     """Dense A from unit volumes and dense A^T from unit projections agree bitwise."""
     import torch
@@ -96,7 +114,12 @@ def test_gpu_pair_is_exact_transpose(orc, lib, name):
         AT[:, r] = x.view(-1).cpu().numpy()
     assert np.array_equal(A.T, AT)
     Ao = orc.dense_A(og)
-    assert np.array_equal(A != 0, Ao != 0) or np.sum((A != 0) != (Ao != 0)) <= 2
+    # Same sparsity pattern, except that a ray through a voxel edge or corner (a
+    # measure-zero tie: in "one_view" the rays with |u| = |v| have y = z all
+    # along) may leave a rounding-sized chord in a side cell, in either matrix.
+    diff = (A != 0) != (Ao != 0)
+    tiny = 1e-5 * min(og.vx, og.vy, og.vz)
+    assert np.all(np.maximum(np.abs(A[diff]), np.abs(Ao[diff])) <= tiny)
     np.testing.assert_allclose(A, Ao, rtol=0, atol=2e-5 * np.abs(Ao).max())
 
 

@@ -209,3 +209,16 @@ def test_piple_on_ragged_geometry_and_mixed(orc, lib):
                            lib.SolveParams(0.5, 1.5, 0.2, 2, 4, precision=pr,
                                            method=lib.METHOD_PIPLE))
         assert rel(xg, ref.x) <= 1e-3
+
+
+def test_zero_data_breaks_down_immediately(orc, lib):
+    """b = 0 from x_0 = x_p = 0: the first beta is 0, every outer step stops at
+    once (breakdown), x stays 0 -- as in the oracle."""
+    d, og, prior, cur, b, sp = c1_inputs(orc)
+    z = np.zeros(og.vol_shape)
+    zb = np.zeros(og.proj_shape)
+    ref = orc.irn_piccs(og, zb, z, z, sp["alpha"], sp["lam"], sp["tau"], 2, 3)
+    assert ref.breakdown and not np.any(ref.x)
+    xg, rep = _gpu_solve(lib, d, zb, z, z, lib.SolveParams(sp["alpha"], sp["lam"], sp["tau"], 2, 3))
+    assert not np.any(xg)
+    assert rep["inner_done"] == 0 and rep["breakdown"] == 2 and rep["outer_done"] == 2
