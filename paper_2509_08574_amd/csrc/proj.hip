@@ -153,8 +153,20 @@ struct FwdLane {
         }
         const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
             (void *)(vol_m + (size_t)enext.y * Z * E::size), 0, nrec, kBufWord3);
-        nlo = E::load(rs, ob);
-        nhi = E::load(rs, ob + E::size);
+        // The next segment reads its second cell (k + DIR) only if it crosses a z
+        // plane; otherwise that cell's chord is exactly 0 and the read is skipped
+        // (0 stands in, so the product adds exactly nothing).  Reads are the
+        // projector's limit (lane data delivered by the L1), not arithmetic.
+        const bool next_crosses = an < __int_as_float(enext.x);
+        if constexpr (DIR > 0) {
+            nlo = E::load(rs, ob);
+            nhi = 0.0f;
+            if (next_crosses) nhi = E::load(rs, ob + E::size);
+        } else {
+            nhi = E::load(rs, ob + E::size);
+            nlo = 0.0f;
+            if (next_crosses) nlo = E::load(rs, ob);
+        }
         if constexpr (MODE != FWD_COUNT) {
             acc = fmaf(c0, vcur, acc);
             acc = fmaf(c1, vnext, acc);
@@ -427,25 +439,39 @@ k_back(GeoK G, const float *__restrict__ yhat, float *__restrict__ out, const in
     const float a_ref_dv = a_ref * G.dv, fv_off = 0.5f * G.nv - 0.5f - 1e-3f;
     const float rwin = (float)(G.nv - C);  // last allowed window start
 
+    // The detector footprint of the column is the same for every lane: once per
+    // 64 views lane t computes it for view view + t, and each view then reads
+    // its own back with readlane instead of all 64 lanes recomputing it.
+    int fu0v = 0, fu1v = -1;
     for (int view = 0; view < G.nviews; ++view) {
-        const float2 cs = G.trig[view];
-        // detector u range of the column's x-y square: a ray with a positive chord
-        // crosses the square's interior, so its pixel lies strictly between the
-        // extreme corner images (the small margin covers the approximate reciprocal)
-        float umin = 3.0e38f, umax = -3.0e38f;
+        const int tv = view & 63;
+        if (tv == 0) {
+            // detector u range of the column's x-y square: a ray with a positive
+            // chord crosses the square's interior, so its pixel lies strictly between
+            // the extreme corner images (the small margin covers the approximate
+            // reciprocal)
+            const int vw = view + lane;
+            fu0v = 0;
+            fu1v = -1;
+            if (vw < G.nviews) {
+                const float2 cs = G.trig[vw];
+                float umin = 3.0e38f, umax = -3.0e38f;
 #pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            const float X = (c & 1) ? xhi : xlo, Y = (c & 2) ? yhi : ylo;
-            const float depth = G.dso - (X * cs.x + Y * cs.y);
-            const float lat = Y * cs.x - X * cs.y;
-            const float fu = fmaf(lat * __builtin_amdgcn_rcpf(depth), fu_scale, fu_off);
-            umin = fminf(umin, fu);
-            umax = fmaxf(umax, fu);
+                for (int c = 0; c < 4; ++c) {
+                    const float X = (c & 1) ? xhi : xlo, Y = (c & 2) ? yhi : ylo;
+                    const float depth = G.dso - (X * cs.x + Y * cs.y);
+                    const float lat = Y * cs.x - X * cs.y;
+                    const float fu =
+                        fmaf(lat * __builtin_amdgcn_rcpf(depth), fu_scale, fu_off);
+                    umin = fminf(umin, fu);
+                    umax = fmaxf(umax, fu);
+                }
+                fu0v = max(0, (int)ceilf(umin - 1e-3f));
+                fu1v = min(G.nu - 1, (int)floorf(umax + 1e-3f));
+            }
         }
-        // every lane computed the same range: keep it in scalar registers
-        const int iu0 = __builtin_amdgcn_readfirstlane(max(0, (int)ceilf(umin - 1e-3f)));
-        const int iu1 =
-            __builtin_amdgcn_readfirstlane(min(G.nu - 1, (int)floorf(umax + 1e-3f)));
+        const int iu0 = __builtin_amdgcn_readlane(fu0v, tv);
+        const int iu1 = __builtin_amdgcn_readlane(fu1v, tv);
         for (int iu = iu0; iu <= iu1; ++iu) {
             const float4 cxy = G.xy[(size_t)view * G.nu + iu];
             const float ex0 = plane_alpha(px, cxy.x, cxy.y);
