@@ -153,19 +153,27 @@ struct FwdLane {
         }
         const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
             (void *)(vol_m + (size_t)enext.y * Z * E::size), 0, nrec, kBufWord3);
-        // The next segment reads its second cell (k + DIR) only if it crosses a z
-        // plane; otherwise that cell's chord is exactly 0 and the read is skipped
-        // (0 stands in, so the product adds exactly nothing).  Reads are the
-        // projector's limit (lane data delivered by the L1), not arithmetic.
-        const bool next_crosses = an < __int_as_float(enext.x);
-        if constexpr (DIR > 0) {
-            nlo = E::load(rs, ob);
-            nhi = 0.0f;
-            if (next_crosses) nhi = E::load(rs, ob + E::size);
+        if constexpr (DT == CBCT_F32) {
+            // The next segment reads its second cell (k + DIR) only if it crosses
+            // a z plane; otherwise that cell's chord is exactly 0 and the read is
+            // skipped (0 stands in, so the product adds exactly nothing).  With
+            // float32 storage the reads are the projector's limit (lane data
+            // delivered by the L1), not arithmetic.
+            const bool next_crosses = an < __int_as_float(enext.x);
+            if constexpr (DIR > 0) {
+                nlo = E::load(rs, ob);
+                nhi = 0.0f;
+                if (next_crosses) nhi = E::load(rs, ob + E::size);
+            } else {
+                nhi = E::load(rs, ob + E::size);
+                nlo = 0.0f;
+                if (next_crosses) nlo = E::load(rs, ob);
+            }
         } else {
+            // 16-bit storage halves the data; a masked 16-bit read would be merged
+            // into half a register and waited for at once, so both cells are read
+            nlo = E::load(rs, ob);
             nhi = E::load(rs, ob + E::size);
-            nlo = 0.0f;
-            if (next_crosses) nlo = E::load(rs, ob);
         }
         if constexpr (MODE != FWD_COUNT) {
             acc = fmaf(c0, vcur, acc);
