@@ -125,12 +125,22 @@ struct Elem<CBCT_F16> {
 // One x-y segment [aa, ab] of a row's walk: chords c0 (cell k) and c1 (cell
 // k + DIR), z-crossing update, then the next column's reads are issued before
 // this segment's products so their latency overlaps the arithmetic.
+//
+// The z state is the integer index pk of the current cell's exit plane
+// (relative to nz / 2); the exit plane's parameter is fma(pk, rg, cz) and the
+// lower of the two cells read sits at byte offset (pk + nz/2 + 1) * size from
+// one cell below the column, in both directions.  Moving up, a ray that has
+// left the volume reads the next column's bottom pad and then offsets past
+// the buffer record (both read as zero), so only the downward walk needs a
+// clamp, at offset 0.
 template <int DIR, int MODE, int DT>
 struct FwdLane {
     using E = Elem<DT>;
-    float aa, an, pe, rg, cz, acc;
+    float aa, an, rg, cz, acc;
+    int pk;           // exit plane of the current cell, relative to nz / 2
     int ob;           // byte offset of the lower cell read, from one cell below the column
-    int obmax, nrec, Z, nz;
+    int obase;        // nz / 2 + 1
+    int nrec, Z, nz;
     const char *vol_m;
     unsigned cnt;
 
@@ -146,11 +156,14 @@ struct FwdLane {
             cnt += (c0 > 0.0f && kc >= 0 && kc < nz) ? 1u : 0u;
             cnt += (c1 > 0.0f && kc + DIR >= 0 && kc + DIR < nz) ? 1u : 0u;
         }
-        if (an < ab) {
-            pe += (float)DIR;
-            an = plane_alpha(pe, rg, cz);
-            ob = DIR > 0 ? min(ob + E::size, obmax) : max(ob - E::size, 0);
-        }
+        // at most one z plane per segment: step the plane index by 0 or DIR and
+        // re-evaluate the exit plane either way (the same fma on the same index
+        // gives the same value), rather than selecting between two candidates
+        const int cross = an < ab ? 1 : 0;
+        pk += DIR > 0 ? cross : -cross;
+        an = plane_alpha((float)pk, rg, cz);
+        ob = (pk + obase) * E::size;
+        if constexpr (DIR < 0) ob = max(ob, 0);
         const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
             (void *)(vol_m + (size_t)enext.y * Z * E::size), 0, nrec, kBufWord3);
         if constexpr (DT == CBCT_F32) {
@@ -202,14 +215,16 @@ __device__ __forceinline__ void fwd_walk(const GeoK &G, const void *vol, const i
 #pragma unroll
     for (int p = 0; p < RPL; ++p) {
         int k;
-        zlane_init(a_in, czr[p], G.nz, k, L[p].pe, L[p].an);
+        float pe;
+        zlane_init(a_in, czr[p], G.nz, k, pe, L[p].an);
         L[p].aa = a_in;
         L[p].rg = czr[p].y;
         L[p].cz = czr[p].z;
         L[p].acc = 0.0f;
         L[p].cnt = 0;
-        L[p].ob = (k + (DIR > 0 ? 2 : 1)) * E::size;
-        L[p].obmax = (G.nz + 2) * E::size;
+        L[p].pk = (int)pe;
+        L[p].obase = (G.nz >> 1) + 1;
+        L[p].ob = (k + (DIR > 0 ? 2 : 1)) * E::size;  // = (pk + obase) * size
         L[p].nrec = (G.nz + 4) * E::size;
         L[p].Z = G.Z;
         L[p].nz = G.nz;
