@@ -167,7 +167,7 @@ def _sample_voxels(g, rng, n):
     return np.array(vox, dtype=np.int64)
 
 
-@pytest.mark.parametrize("cfg", ["c2", "c5"])
+@pytest.mark.parametrize("cfg", ["c2", "c3_512", "c5"])
 def test_full_size_sampled_parity(orc, lib, cfg):
     """Full-size launch (as benchmarked); oracle evaluates sampled rays and voxels."""
     import torch

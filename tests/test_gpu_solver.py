@@ -222,3 +222,28 @@ def test_zero_data_breaks_down_immediately(orc, lib):
     xg, rep = _gpu_solve(lib, d, zb, z, z, lib.SolveParams(sp["alpha"], sp["lam"], sp["tau"], 2, 3))
     assert not np.any(xg)
     assert rep["inner_done"] == 0 and rep["breakdown"] == 2 and rep["outer_done"] == 2
+
+
+def test_full_size_lsqr_residual_estimate(lib):
+    """256^3 / 90 views / 512^2, the benchmarked launch shape.  With alpha = lambda
+    = 0 one outer step is plain LSQR, whose phibar_k equals ||b - A x_k|| in exact
+    arithmetic and never grows (Sec. 2.2.2).  After 10 steps the device's estimate
+    must match the residual recomputed with one more forward projection (float64
+    norm) to 1e-5 (float32 vectors drift by ~1e-7 here): a property that holds at
+    any size, so no oracle solve is needed."""
+    import torch
+    from paper_2509_08574_amd import synth
+    gg = lib.Geometry.from_dict(synth.geometry("c2"))
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(11)
+    xt = torch.rand(gg.vol_shape, device="cuda", generator=gen)
+    b = lib.forward(gg, xt)
+    b += 0.01 * b.mean() * torch.randn(b.shape, device="cuda", generator=gen)
+    x = torch.zeros_like(xt)
+    x, rep = lib.solve(gg, b, torch.zeros_like(xt), x, lib.SolveParams(0.0, 0.0, 0.1, 1, 10))
+    ph = np.array(rep["phibar"])
+    assert rep["inner_done"] == 10 and rep["outer_done"] == 1 and rep["breakdown"] == 0
+    assert np.all(np.diff(ph) <= 0.0)
+    assert ph[-1] < 0.5 * ph[0]
+    true = float(torch.linalg.norm((b - lib.forward(gg, x)).double()))
+    assert abs(ph[-1] - true) <= 1e-5 * true
