@@ -246,10 +246,22 @@ k_red(const double *__restrict__ p0, int64_t n0, const double *__restrict__ p1, 
         return;
     }
     __shared__ double red[1024];
-    double s = 0.0;
-    for (int64_t t = threadIdx.x; t < n0; t += 1024) s += p0[t];
-    for (int64_t t = threadIdx.x; t < n1; t += 1024) s += p1[t];
-    red[threadIdx.x] = s;
+    // eight independent sums per thread keep eight reads in flight (this one block
+    // is all that runs on the GPU meanwhile); combined in a fixed order
+    double a[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    auto add = [&](const double *__restrict__ p, int64_t n) {
+        int64_t t = threadIdx.x;
+        for (; t + 7 * 1024 < n; t += 8 * 1024) {
+#pragma unroll
+            for (int u = 0; u < 8; ++u) a[u] += p[t + u * 1024];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            if (t + u * 1024 < n) a[u] += p[t + u * 1024];
+    };
+    add(p0, n0);
+    add(p1, n1);
+    red[threadIdx.x] = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
     __syncthreads();
     for (int h = 512; h > 0; h >>= 1) {
         if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
