@@ -4,19 +4,19 @@
 // read as exact ray/voxel chord lengths; Krylov solvers touch it only through
 // products with A and A^T (Sec. 2.2.2).  Chord arithmetic: chord.h.
 //
-// Forward (k_fwd): one wave per (view, detector column u, 64 detector rows);
-// lane = row.  All rays of one detector column share their x-y path, so the
-// wave walks the voxel columns (i, j) it crosses in lock-step (uniform control
-// flow) while every lane tracks its own z cell.  Volumes are stored column-
-// major (z fastest), so at each step the 64 lanes read a short contiguous run
-// of one column: coalesced gathers for every view angle.
+// Forward (k_fwd): one wave per (view, detector column u, 64 or 128 detector
+// rows); each lane walks one or two rows.  All rays of one detector column
+// share their x-y path, so the wave walks the voxel columns (i, j) it crosses
+// in lock-step (uniform control flow) while every lane tracks its own z cell.
+// Volumes are stored column-major (z fastest), so at each step the lanes read a
+// short contiguous run of one column: coalesced gathers for every view angle.
 //
-// Back (k_back): one wave per voxel column (i, j), four columns per block.
-// For every view, the wave visits the detector columns u whose rays cross
-// (i, j), recomputes the same x-y interval [aa, ab] and the same z state as
-// the forward kernel, and adds c0 * y to cell k and c1 * y to cell k + s of a
-// per-wave LDS copy of the column.  Each column is written to HBM once, with
-// no global atomics.
+// Back (k_back): one wave per voxel column (i, j), columns taken in 16 x 16
+// tiles.  For every view, the wave visits the detector columns u whose rays
+// cross (i, j) and recomputes the forward walk's x-y interval [aa, ab]; each
+// lane then gathers, for each of its cells, a short window of detector rows
+// whose chords with that cell are the forward kernel's c0 / c1 bit for bit.
+// Every cell is summed in a fixed order and written once; no atomics.
 #include <hip/hip_fp16.h>
 
 #include <algorithm>
