@@ -123,6 +123,17 @@ def projector_roofline(args, cbct, torch, g, xc, ywc, stream):
                             "unit": "G wave-instructions/s",
                             "frac": round(rate / VALU_PEAK_WAVE_INSTR_S, 4),
                             "instructions_per_launch": valu}
+    # which resource binds: the operand-bytes figure above is not the HBM traffic
+    # (most operands come from L2); beside it, the measured utilisations
+    ta = recorded_profile(dom[0], args.workload, "ta_busy_fraction")
+    td = recorded_profile(dom[0], args.workload, "td_busy_fraction")
+    l2 = recorded_profile(dom[0], args.workload, "l2_hit_rate")
+    if traffic and ta is not None and td is not None:
+        util = {"hbm_traffic": round(traffic / (dom[1] * 1e-3) / 1e9 / HBM_PEAK_GBS, 3),
+                "valu_issue": roofline["valu"]["frac"] if "valu" in roofline else None,
+                "texture_address": ta, "texture_data": td}
+        roofline["measured"] = dict(util, l2_hit_rate=l2)
+        roofline["binds"] = [k for k, v in util.items() if v is not None and v >= 0.85]
     return t_fwd, t_back, nnz, gvp_fwd, gvp_back, roofline
 
 
