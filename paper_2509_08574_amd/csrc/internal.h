@@ -158,6 +158,12 @@ struct FwdArgs {
     unsigned long long *count;  // FWD_COUNT
     float scale;             // FWD_PLAIN: output multiplier (value of one stored unit)
 };
+// Internal storage codes beyond cbct_dtype: the solver's 16-bit shadow of a
+// volume kept as one 32-bit word per cell holding (cell k, cell k + 1) in its
+// low and high halves, so that one aligned read yields both cells a ray step
+// may need.  Word k of a column is (h(v[k]), h(v[k+1])), pads included.
+constexpr int CBCT_BF16_PAIR = 16, CBCT_F16_PAIR = 17;
+
 void launch_forward(const GeoK &G, int mode, const FwdArgs &a, hipStream_t s,
                     int dtype = CBCT_F32);
 int64_t forward_blocks(const GeoK &G);

@@ -204,7 +204,7 @@ k_regA(GeoK G, const float *__restrict__ t, const float *__restrict__ W1,
 template <int DT>
 __global__ void __launch_bounds__(256)
 k_xw(float *__restrict__ x, float *__restrict__ w, const float *__restrict__ V,
-     unsigned short *__restrict__ V16, int64_t n, const double *sc, const int *brk) {
+     unsigned *__restrict__ V16, int64_t n, const double *sc, const int *brk) {
     if (*brk == 2) return;
     const float a = (float)sc[SC_XW_A], b = (float)sc[SC_XW_B], c = (float)sc[SC_XW_C];
     const float sv = (float)sc[SC_V16_SCALE];
@@ -214,10 +214,16 @@ k_xw(float *__restrict__ x, float *__restrict__ w, const float *__restrict__ V,
         if (a != 0.0f) x[t] = fmaf(a, wo, x[t]);
         const float v = V[t];
         w[t] = fmaf(c, wo, b * v);
+        // shadow word t = (h(V[t]), h(V[t + 1])): V[t + 1] is the next cell of the
+        // column, or a zero pad / guard
         if constexpr (DT == CBCT_BF16) {
-            V16[t] = __bfloat16_as_ushort(__float2bfloat16(v * sv));
+            const unsigned h0 = __bfloat16_as_ushort(__float2bfloat16(v * sv));
+            const unsigned h1 = __bfloat16_as_ushort(__float2bfloat16(V[t + 1] * sv));
+            V16[t] = h0 | (h1 << 16);
         } else if constexpr (DT == CBCT_F16) {
-            V16[t] = __half_as_ushort(__float2half(v * sv));
+            const unsigned h0 = __half_as_ushort(__float2half(v * sv));
+            const unsigned h1 = __half_as_ushort(__float2half(V[t + 1] * sv));
+            V16[t] = h0 | (h1 << 16);
         }
     }
 }
@@ -346,8 +352,8 @@ __global__ void k_solve_end(double *sc, int *fl) {
 
 struct Workspace {
     float *x, *xp, *w, *V, *t, *W1, *W2, *u1, *u2;  // padded column bases (P pointers)
-    unsigned short *V16;                            // 16-bit shadow base (P), mixed forms
-    unsigned short *V16buf;                         // its allocation start
+    unsigned *V16;      // 16-bit shadow of V as pair words (base P), mixed forms
+    unsigned *V16buf;   // its allocation start
     size_t v16_bytes;
     int64_t cstride;                                // floats between components
     float *bhat, *uhat;
@@ -379,8 +385,8 @@ static Workspace carve(const cbct_geom *g, const GeoK &G, const piccs_params *p,
     W.u1 = P(7); W.u2 = P(10);
     W.cstride = (int64_t)(vb / sizeof(float));
     if (p->precision != CBCT_PREC_FP32) {
-        W.v16_bytes = al(sizeof(unsigned short) * (size_t)g->pad_floats());
-        W.V16buf = (unsigned short *)take(W.v16_bytes);
+        W.v16_bytes = al(sizeof(unsigned) * (size_t)g->pad_floats());
+        W.V16buf = (unsigned *)take(W.v16_bytes);
         W.V16 = W.V16buf ? W.V16buf + kGuard : nullptr;
     }
     W.bhat = (float *)take(pb);
@@ -446,7 +452,7 @@ void solve_enqueue(cbct_geom *g, const float *b, const float *xp, float *x,
                                W.V16, ncz, W.sc, W.fl);
         else
             hipLaunchKernelGGL(k_xw<CBCT_F32>, dim3(4096), dim3(256), 0, s, W.x, W.w, W.V,
-                               (unsigned short *)nullptr, ncz, W.sc, W.fl);
+                               (unsigned *)nullptr, ncz, W.sc, W.fl);
     };
     vol_to_cols(G, x, W.x, s);
     vol_to_cols(G, xp, W.xp, s);
@@ -484,7 +490,10 @@ void solve_enqueue(cbct_geom *g, const float *b, const float *xp, float *x,
         for (int ki = 0; ki < p->n_inner; ++ki, ++it_global) {
             fa.vol = dt == CBCT_F32 ? (const void *)W.V : (const void *)W.V16;
             fa.uin = W.uhat; fa.s1 = W.sc + SC_FWD_S1; fa.s2 = W.sc + SC_FWD_S2;
-            launch_forward(G, FWD_SOLVER, fa, s, dt);
+            launch_forward(G, FWD_SOLVER, fa, s,
+                           dt == CBCT_BF16  ? CBCT_BF16_PAIR
+                           : dt == CBCT_F16 ? CBCT_F16_PAIR
+                                            : CBCT_F32);
             hipLaunchKernelGGL(regF_step, dim3(nvb), dim3(256), 0, s, G, W.V,
                                (const float *)nullptr, W.W1, W.W2, W.u1, W.u2, W.cstride,
                                alpha, lam, W.sc + SC_REG_S1, W.sc + SC_REG_S2, W.pr, W.fl);

@@ -121,6 +121,37 @@ struct Elem<CBCT_F16> {
         return __half2float(__ushort_as_half(h));
     }
 };
+// Pair words (CBCT_BF16_PAIR / CBCT_F16_PAIR): 4 bytes per cell, word k holding
+// cells k and k + 1.
+template <>
+struct Elem<CBCT_BF16_PAIR> {
+    static constexpr int size = 4;
+    __device__ static void load2(__amdgpu_buffer_rsrc_t r, int off, float &lo, float &hi) {
+        const unsigned w = __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0);
+        lo = __uint_as_float(w << 16);
+        hi = __uint_as_float(w & 0xffff0000u);
+    }
+};
+template <>
+struct Elem<CBCT_F16_PAIR> {
+    static constexpr int size = 4;
+    __device__ static void load2(__amdgpu_buffer_rsrc_t r, int off, float &lo, float &hi) {
+        const unsigned w = __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0);
+        lo = __half2float(__ushort_as_half((unsigned short)(w & 0xffffu)));
+        hi = __half2float(__ushort_as_half((unsigned short)(w >> 16)));
+    }
+};
+template <int DT>
+constexpr bool kPairs = DT == CBCT_BF16_PAIR || DT == CBCT_F16_PAIR;
+
+// Bytes of one column's buffer record, counted from one cell below the column:
+// reads past it return 0.  Single cells: up to cell nz + 1 (the next column's
+// bottom pad).  Pair words: up to word nz (top pad and the next column's bottom
+// pad); word nz + 1 would carry the next column's first cell in its high half.
+template <int DT>
+__host__ __device__ constexpr int fwd_record_bytes(int nz) {
+    return kPairs<DT> ? (nz + 3) * 4 : (nz + 4) * Elem<DT>::size;
+}
 
 // One x-y segment [aa, ab] of a row's walk: chords c0 (cell k) and c1 (cell
 // k + DIR), z-crossing update, then the next column's reads are issued before
@@ -182,6 +213,10 @@ struct FwdLane {
                 nlo = 0.0f;
                 if (next_crosses) nlo = E::load(rs, ob);
             }
+        } else if constexpr (kPairs<DT>) {
+            // one aligned word holds both cells: (k, k + 1) moving up, (k - 1, k)
+            // moving down
+            E::load2(rs, ob, nlo, nhi);
         } else {
             // 16-bit storage halves the data; a masked 16-bit read would be merged
             // into half a register and waited for at once, so both cells are read
@@ -211,7 +246,8 @@ __device__ __forceinline__ void fwd_walk(const GeoK &G, const void *vol, const i
     int2 e0 = sp[0], e1 = sp[1], e2 = sp[2];
     const char *vol_m = (const char *)vol - E::size;
     const __amdgpu_buffer_rsrc_t rs0 = __builtin_amdgcn_make_buffer_rsrc(
-        (void *)(vol_m + (size_t)e0.y * G.Z * E::size), 0, (G.nz + 4) * E::size, kBufWord3);
+        (void *)(vol_m + (size_t)e0.y * G.Z * E::size), 0, fwd_record_bytes<DT>(G.nz),
+        kBufWord3);
 #pragma unroll
     for (int p = 0; p < RPL; ++p) {
         int k;
@@ -225,12 +261,16 @@ __device__ __forceinline__ void fwd_walk(const GeoK &G, const void *vol, const i
         L[p].pk = (int)pe;
         L[p].obase = (G.nz >> 1) + 1;
         L[p].ob = (k + (DIR > 0 ? 2 : 1)) * E::size;  // = (pk + obase) * size
-        L[p].nrec = (G.nz + 4) * E::size;
+        L[p].nrec = fwd_record_bytes<DT>(G.nz);
         L[p].Z = G.Z;
         L[p].nz = G.nz;
         L[p].vol_m = vol_m;
-        a0[p] = E::load(rs0, L[p].ob);
-        a1[p] = E::load(rs0, L[p].ob + E::size);
+        if constexpr (kPairs<DT>) {
+            E::load2(rs0, L[p].ob, a0[p], a1[p]);
+        } else {
+            a0[p] = E::load(rs0, L[p].ob);
+            a1[p] = E::load(rs0, L[p].ob + E::size);
+        }
     }
     // Entries past the last segment are no-op segments (zero length, exit
     // parameter, column 0), so the walk runs in whole pairs and reads table
@@ -379,6 +419,10 @@ void launch_forward(const GeoK &G, int mode, const FwdArgs &a, hipStream_t s, in
         launch_forward_dt<CBCT_BF16>(G, mode, a, s, grid);
     else if (dtype == CBCT_F16)
         launch_forward_dt<CBCT_F16>(G, mode, a, s, grid);
+    else if (dtype == CBCT_BF16_PAIR)
+        launch_forward_dt<CBCT_BF16_PAIR>(G, mode, a, s, grid);
+    else if (dtype == CBCT_F16_PAIR)
+        launch_forward_dt<CBCT_F16_PAIR>(G, mode, a, s, grid);
     else
         launch_forward_dt<CBCT_F32>(G, mode, a, s, grid);
     CBCT_HIP(hipGetLastError());
