@@ -195,7 +195,10 @@ typedef struct {
     int32_t n_outer;  /* IRN reweightings                                         */
     int32_t n_inner;  /* LSQR iterations per reweighting (total = outer * inner)  */
     int32_t precision;/* cbct_precision                                           */
-    int32_t reorth;   /* 0: none (the paper's short recurrences); 1: reserved      */
+    int32_t reorth;   /* 0: none (the paper's short recurrences); 1: one-sided     */
+                      /* reorthogonalisation of v: classical Gram-Schmidt twice   */
+                      /* against this outer step's v's, float64 arithmetic; adds  */
+                      /* n_inner volumes to the workspace (not in the paper)      */
     int32_t method;   /* cbct_method: which prior term the third block encodes     */
 } piccs_params;
 
@@ -217,8 +220,10 @@ int piccs_workspace_bytes(const cbct_geom *g, const piccs_params *p, size_t *byt
  *   [A; alpha W1 D; lambda W2 D] x ~ [b; 0; lambda W2 D x_p]
  * restarted from x_{k-1}.  With p->method = CBCT_METHOD_PIPLE the third block is
  * lambda I with right-hand side lambda x_p (IRN-PIPLE, Sec. 2.2.1, eq. "seq_W_2").
- * lambda = 0 gives IRN-TV and alpha = lambda = 0 plain least squares.  The LSQR scalars (norms, Givens rotation) are kept
- * in FP64 on the device; the host never waits inside the solve.
+ * lambda = 0 gives IRN-TV and alpha = lambda = 0 plain least squares.  The
+ * LSQR scalars (norms, Givens rotation) are kept in FP64 on the device; the
+ * host never waits inside the solve.  p->reorth = 1 adds a one-sided
+ * reorthogonalisation of v (not in the paper; see piccs_params).
  * b[view][v][u], xp and x[z][y][x] are float32 device arrays; x holds x_0 on
  * entry (warm start) and x_K on return.  workspace: >= piccs_workspace_bytes,
  * device, 256-byte aligned.  If rep != NULL the call synchronises the stream
@@ -268,7 +273,7 @@ typedef struct {
     int32_t patient;       /* id given to cbct_server_add_prior                     */
     cbct_geom_desc geom;   /* scan geometry; its volume must be the patient's       */
     const float *b_host;   /* HOST projections b[view][v][u]; copied at submit      */
-    piccs_params params;   /* solve parameters (reorth must be 0)                   */
+    piccs_params params;   /* solve parameters                                      */
     int32_t x0;            /* cbct_x0_source                                        */
 } cbct_request;
 

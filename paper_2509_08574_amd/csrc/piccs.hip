@@ -204,7 +204,8 @@ k_regA(GeoK G, const float *__restrict__ t, const float *__restrict__ W1,
 template <int DT>
 __global__ void __launch_bounds__(256)
 k_xw(float *__restrict__ x, float *__restrict__ w, const float *__restrict__ V,
-     unsigned *__restrict__ V16, int64_t n, const double *sc, const int *brk) {
+     unsigned *__restrict__ V16, float *__restrict__ q, int64_t n, const double *sc,
+     const int *brk) {
     if (*brk == 2) return;
     const float a = (float)sc[SC_XW_A], b = (float)sc[SC_XW_B], c = (float)sc[SC_XW_C];
     const float sv = (float)sc[SC_V16_SCALE];
@@ -214,6 +215,7 @@ k_xw(float *__restrict__ x, float *__restrict__ w, const float *__restrict__ V,
         if (a != 0.0f) x[t] = fmaf(a, wo, x[t]);
         const float v = V[t];
         w[t] = fmaf(c, wo, b * v);
+        if (q) q[t] = b * v;  // normalised v, kept for reorthogonalisation
         // shadow word t = (h(V[t]), h(V[t + 1])): V[t + 1] is the next cell of the
         // column, or a zero pad / guard
         if constexpr (DT == CBCT_BF16) {
@@ -226,6 +228,64 @@ k_xw(float *__restrict__ x, float *__restrict__ w, const float *__restrict__ V,
             V16[t] = h0 | (h1 << 16);
         }
     }
+}
+
+// ---------------------------------------------------------------- reorthogonalisation
+
+// Optional one-sided reorthogonalisation of LSQR's v (not in the paper, whose
+// method relies on the short recurrences): classical Gram-Schmidt applied twice
+// against the normalised v's of the current outer step, q_0 .. q_{k-1}, with
+// float64 arithmetic.  One pass: c_i = <q_i, V> for all i from the same V
+// (k_qdot per-block partials, k_qred fixed-order sums), then
+// V <- V - sum_i c_i q_i (k_qaxpy), which also leaves per-block partials of
+// |V|^2 for the norm that follows.
+constexpr int kQBlocks = 1024;
+
+// grid (kQBlocks, k): block (b, i) sums q_i[t] V[t] over its grid-stride share.
+__global__ void __launch_bounds__(256)
+k_qdot(const float *__restrict__ Q, int64_t qstride, const float *__restrict__ V, int64_t n,
+       double *part, const int *brk) {
+    if (*brk == 2) return;
+    const float *q = Q + (int64_t)blockIdx.y * qstride;
+    double s = 0.0;
+    for (int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x; t < n; t += (int64_t)kQBlocks * 256)
+        s += (double)q[t] * (double)V[t];
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+    __shared__ double red[4];
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0)
+        part[(int64_t)blockIdx.y * kQBlocks + blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+// grid (k), 1024 threads: coef[i] = sum of the kQBlocks partials of q_i, fixed order.
+__global__ void __launch_bounds__(1024)
+k_qred(const double *__restrict__ part, double *coef, const int *brk) {
+    if (*brk == 2) return;
+    __shared__ double red[1024];
+    red[threadIdx.x] = part[(int64_t)blockIdx.x * kQBlocks + threadIdx.x];
+    __syncthreads();
+    for (int h = 512; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) coef[blockIdx.x] = red[0];
+}
+
+// grid kQBlocks: V <- V - sum_{i<k} coef[i] q_i (float64), partials of |V|^2.
+__global__ void __launch_bounds__(256)
+k_qaxpy(const float *__restrict__ Q, int64_t qstride, float *__restrict__ V, int64_t n, int k,
+        const double *__restrict__ coef, double *part, const int *brk) {
+    if (*brk == 2) return;
+    double sum = 0.0;
+    for (int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x; t < n; t += (int64_t)kQBlocks * 256) {
+        double v = (double)V[t];
+        for (int i = 0; i < k; ++i) v -= coef[i] * (double)Q[(int64_t)i * qstride + t];
+        const float vf = (float)v;
+        V[t] = vf;
+        sum += (double)vf * (double)vf;
+    }
+    block_partial(sum, part);
 }
 
 // Power-of-two scale bringing the entries of a vector of norm nrm over m
@@ -359,6 +419,8 @@ struct Workspace {
     float *bhat, *uhat;
     double *pf, *pr, *pa;  // partials: forward, regF, regA
     int64_t nf, nr;
+    float *Q;              // reorthogonalisation basis: n_inner padded volumes (base P)
+    double *pq, *qcoef;    // its dot partials [n_inner][kQBlocks] and coefficients
     double *sc, *hist;
     int *fl;
     size_t bytes;
@@ -394,6 +456,12 @@ static Workspace carve(const cbct_geom *g, const GeoK &G, const piccs_params *p,
     W.pf = (double *)take(sizeof(double) * (size_t)W.nf);
     W.pr = (double *)take(sizeof(double) * (size_t)W.nr);
     W.pa = (double *)take(sizeof(double) * (size_t)W.nr);
+    if (p->reorth) {
+        W.pq = (double *)take(sizeof(double) * (size_t)kQBlocks * p->n_inner);
+        W.qcoef = (double *)take(sizeof(double) * (size_t)p->n_inner);
+        float *q0 = (float *)take(vb * (size_t)p->n_inner);
+        W.Q = q0 ? q0 + kGuard : nullptr;
+    }
     W.sc = (double *)take(sizeof(double) * SC_COUNT);
     W.fl = (int *)take(sizeof(int) * 16);
     W.hist = (double *)take(sizeof(double) * (size_t)std::max(1, p->n_outer * p->n_inner));
@@ -411,7 +479,7 @@ void check_solve_params(const piccs_params *p) {
     CBCT_REQUIRE(p->precision == CBCT_PREC_FP32 || p->precision == CBCT_PREC_MIXED_BF16 ||
                      p->precision == CBCT_PREC_MIXED_F16,
                  "unknown precision");
-    CBCT_REQUIRE(p->reorth == 0, "reorthogonalisation is not available in this build");
+    CBCT_REQUIRE(p->reorth == 0 || p->reorth == 1, "reorth must be 0 or 1");
     CBCT_REQUIRE(p->method == CBCT_METHOD_PICCS || p->method == CBCT_METHOD_PIPLE,
                  "unknown method");
 }
@@ -443,16 +511,30 @@ void solve_enqueue(cbct_geom *g, const float *b, const float *xp, float *x,
                                                           : CBCT_F32;
     if (dt != CBCT_F32) launch_fill((float *)W.V16buf, (int64_t)(W.v16_bytes / 4), 0.0f, s);
     const double nvox = (double)g->n_vox();
-    auto xw = [&]() {
+    // q: where the normalised v goes for reorthogonalisation, or null
+    auto xw = [&](float *q) {
         if (dt == CBCT_BF16)
             hipLaunchKernelGGL(k_xw<CBCT_BF16>, dim3(4096), dim3(256), 0, s, W.x, W.w, W.V,
-                               W.V16, ncz, W.sc, W.fl);
+                               W.V16, q, ncz, W.sc, W.fl);
         else if (dt == CBCT_F16)
             hipLaunchKernelGGL(k_xw<CBCT_F16>, dim3(4096), dim3(256), 0, s, W.x, W.w, W.V,
-                               W.V16, ncz, W.sc, W.fl);
+                               W.V16, q, ncz, W.sc, W.fl);
         else
             hipLaunchKernelGGL(k_xw<CBCT_F32>, dim3(4096), dim3(256), 0, s, W.x, W.w, W.V,
-                               (unsigned *)nullptr, ncz, W.sc, W.fl);
+                               (unsigned *)nullptr, q, ncz, W.sc, W.fl);
+    };
+    const bool reorth = p->reorth != 0;
+    auto basis = [&](int i) { return reorth && i < p->n_inner ? W.Q + (int64_t)i * W.cstride
+                                                             : (float *)nullptr; };
+    // CGS2 of V against q_0 .. q_{k-1}; the second pass leaves |V|^2 partials in W.pq
+    auto cgs2 = [&](int k) {
+        for (int pass = 0; pass < 2; ++pass) {
+            hipLaunchKernelGGL(k_qdot, dim3(kQBlocks, k), dim3(256), 0, s, W.Q, W.cstride, W.V,
+                               ncz, W.pq, W.fl);
+            hipLaunchKernelGGL(k_qred, dim3(k), dim3(1024), 0, s, W.pq, W.qcoef, W.fl);
+            hipLaunchKernelGGL(k_qaxpy, dim3(kQBlocks), dim3(256), 0, s, W.Q, W.cstride, W.V,
+                               ncz, k, W.qcoef, W.pq, W.fl);
+        }
     };
     vol_to_cols(G, x, W.x, s);
     vol_to_cols(G, xp, W.xp, s);
@@ -486,7 +568,7 @@ void solve_enqueue(cbct_geom *g, const float *b, const float *xp, float *x,
         hipLaunchKernelGGL(k_red<RED_INIT_ALPHA>, dim3(1), dim3(1024), 0, s, W.pa, W.nr,
                            (const double *)nullptr, (int64_t)0, W.sc, W.fl, W.hist, 0, dt,
                            nvox);
-        xw();
+        xw(basis(0));
         for (int ki = 0; ki < p->n_inner; ++ki, ++it_global) {
             fa.vol = dt == CBCT_F32 ? (const void *)W.V : (const void *)W.V16;
             fa.uin = W.uhat; fa.s1 = W.sc + SC_FWD_S1; fa.s2 = W.sc + SC_FWD_S2;
@@ -503,10 +585,12 @@ void solve_enqueue(cbct_geom *g, const float *b, const float *xp, float *x,
             hipLaunchKernelGGL(regA, dim3(nvb), dim3(256), 0, s, G, W.t, W.W1, W.W2, W.u1,
                                W.u2, W.cstride, alpha, lam, W.V, W.sc + SC_BACK_S1,
                                W.sc + SC_BACK_S2, W.pa, W.fl);
-            hipLaunchKernelGGL(k_red<RED_ALPHA>, dim3(1), dim3(1024), 0, s, W.pa, W.nr,
+            if (reorth) cgs2(ki + 1);
+            hipLaunchKernelGGL(k_red<RED_ALPHA>, dim3(1), dim3(1024), 0, s,
+                               reorth ? W.pq : W.pa, reorth ? (int64_t)kQBlocks : W.nr,
                                (const double *)nullptr, (int64_t)0, W.sc, W.fl, W.hist,
                                it_global, dt, nvox);
-            xw();
+            xw(basis(ki + 1));
         }
     }
     hipLaunchKernelGGL(k_solve_end, dim3(1), dim3(1), 0, s, W.sc, W.fl);

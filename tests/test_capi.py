@@ -66,9 +66,13 @@ def test_workspace_bytes_and_param_checks(lib):
     assert n < 13 * pad + 2 * 48 * 96 * 96 * 4 + 8 * 1024 * 1024
     assert lib.workspace_bytes(g, lib.SolveParams(1.0, 2.0, 0.1, 3, 5,
                                                   method=lib.METHOD_PIPLE)) == n
+    # reorthogonalisation keeps the outer step's n_inner v's as padded volumes
+    nr = lib.workspace_bytes(g, lib.SolveParams(1.0, 2.0, 0.1, 3, 5, reorth=1))
+    assert nr >= n + 5 * pad
     for bad in (lib.SolveParams(-1.0, 2.0, 0.1, 3, 5), lib.SolveParams(1.0, 2.0, 0.1, 0, 5),
                 lib.SolveParams(1.0, 2.0, float("nan"), 3, 5),
-                lib.SolveParams(1.0, 2.0, 0.1, 3, 5, method=2)):
+                lib.SolveParams(1.0, 2.0, 0.1, 3, 5, method=2),
+                lib.SolveParams(1.0, 2.0, 0.1, 3, 5, reorth=2)):
         with pytest.raises(lib.CbctError):
             lib.workspace_bytes(g, bad)
 
