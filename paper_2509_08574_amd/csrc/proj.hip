@@ -150,7 +150,7 @@ constexpr bool kPairs = DT == CBCT_BF16_PAIR || DT == CBCT_F16_PAIR;
 // pad); word nz + 1 would carry the next column's first cell in its high half.
 template <int DT>
 __host__ __device__ constexpr int fwd_record_bytes(int nz) {
-    return kPairs<DT> ? (nz + 3) * 4 : (nz + 4) * Elem<DT>::size;
+    return kPairs<DT> ? (nz + 2) * 4 : (nz + 3) * Elem<DT>::size;
 }
 
 // One x-y segment [aa, ab] of a row's walk: chords c0 (cell k) and c1 (cell
@@ -172,7 +172,7 @@ struct FwdLane {
     int ob;           // byte offset of the lower cell read, from one cell below the column
     int obase;        // nz / 2 + 1
     int nrec, Z, nz;
-    const char *vol_m;
+    const char *vol_c;
     unsigned cnt;
 
     __device__ __forceinline__ void step(int2 e, float lo, float hi, int2 enext, float &nlo,
@@ -183,7 +183,7 @@ struct FwdLane {
         const float c1 = ab - m;
         const float vcur = DIR > 0 ? lo : hi, vnext = DIR > 0 ? hi : lo;
         if constexpr (MODE == FWD_COUNT) {
-            const int kc = ob / E::size - (DIR > 0 ? 2 : 1);
+            const int kc = ob / E::size - (DIR > 0 ? 1 : 0);
             cnt += (c0 > 0.0f && kc >= 0 && kc < nz) ? 1u : 0u;
             cnt += (c1 > 0.0f && kc + DIR >= 0 && kc + DIR < nz) ? 1u : 0u;
         }
@@ -194,9 +194,10 @@ struct FwdLane {
         pk += DIR > 0 ? cross : -cross;
         an = plane_alpha((float)pk, rg, cz);
         ob = (pk + obase) * E::size;
-        if constexpr (DIR < 0) ob = max(ob, 0);
+        if constexpr (DIR < 0) ob = max(ob, -E::size);
         const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
-            (void *)(vol_m + (size_t)enext.y * Z * E::size), 0, nrec, kBufWord3);
+            (void *)(vol_c + (uint64_t)(uint32_t)enext.y * (uint32_t)(Z * E::size)), 0, nrec,
+            kBufWord3);
         if constexpr (DT == CBCT_F32) {
             // The next segment reads its second cell (k + DIR) only if it crosses
             // a z plane; otherwise that cell's chord is exactly 0 and the read is
@@ -206,11 +207,9 @@ struct FwdLane {
             const bool next_crosses = an < __int_as_float(enext.x);
             if constexpr (DIR > 0) {
                 nlo = E::load(rs, ob);
-                nhi = 0.0f;
                 if (next_crosses) nhi = E::load(rs, ob + E::size);
             } else {
                 nhi = E::load(rs, ob + E::size);
-                nlo = 0.0f;
                 if (next_crosses) nlo = E::load(rs, ob);
             }
         } else if constexpr (kPairs<DT>) {
@@ -242,11 +241,12 @@ __device__ __forceinline__ void fwd_walk(const GeoK &G, const void *vol, const i
                                          unsigned *cnt) {
     using E = Elem<DT>;
     FwdLane<DIR, MODE, DT> L[RPL];
-    float a0[RPL], a1[RPL], b0[RPL], b1[RPL];
+    // b0, b1 start at zero: a skipped second-cell read leaves the previous value
+    float a0[RPL], a1[RPL], b0[RPL] = {}, b1[RPL] = {};
     int2 e0 = sp[0], e1 = sp[1], e2 = sp[2];
-    const char *vol_m = (const char *)vol - E::size;
+    const char *vol_c = (const char *)vol;
     const __amdgpu_buffer_rsrc_t rs0 = __builtin_amdgcn_make_buffer_rsrc(
-        (void *)(vol_m + (size_t)e0.y * G.Z * E::size), 0, fwd_record_bytes<DT>(G.nz),
+        (void *)(vol_c + (size_t)e0.y * G.Z * E::size), 0, fwd_record_bytes<DT>(G.nz),
         kBufWord3);
 #pragma unroll
     for (int p = 0; p < RPL; ++p) {
@@ -259,12 +259,12 @@ __device__ __forceinline__ void fwd_walk(const GeoK &G, const void *vol, const i
         L[p].acc = 0.0f;
         L[p].cnt = 0;
         L[p].pk = (int)pe;
-        L[p].obase = (G.nz >> 1) + 1;
-        L[p].ob = (k + (DIR > 0 ? 2 : 1)) * E::size;  // = (pk + obase) * size
+        L[p].obase = G.nz >> 1;
+        L[p].ob = (k + (DIR > 0 ? 1 : 0)) * E::size;  // = (pk + obase) * size
         L[p].nrec = fwd_record_bytes<DT>(G.nz);
         L[p].Z = G.Z;
         L[p].nz = G.nz;
-        L[p].vol_m = vol_m;
+        L[p].vol_c = vol_c;
         if constexpr (kPairs<DT>) {
             E::load2(rs0, L[p].ob, a0[p], a1[p]);
         } else {
