@@ -504,7 +504,7 @@ k_back(GeoK G, const float *__restrict__ yhat, float *__restrict__ out, const in
     // row index of height z at ray parameter A: z / (A dv) + nv/2 - 1/2; the
     // 1e-3 margin (rows) is folded into the offset
     const float a_ref_dv = a_ref * G.dv, fv_off = 0.5f * G.nv - 0.5f - 1e-3f;
-    const float rwin = (float)(G.nv - C);  // last allowed window start
+    const float nrwin = -(float)(G.nv - C);  // minus the last allowed window start
 
     // The detector footprint of the column is the same for every lane: once per
     // 64 views lane t computes it for view view + t, and each view then reads
@@ -557,11 +557,15 @@ k_back(GeoK G, const float *__restrict__ yhat, float *__restrict__ out, const in
                 if (q >= nq) break;
                 // the first row whose centre can satisfy z_k <= A v, then a window of C
                 // rows kept inside [0, nv): every row meeting the cell is in it, and
-                // rows that miss the cell contribute exactly zero below
-                const float flo = fmaf(zk0[q], zk0[q] >= 0.0f ? iA2 : iA1, fv_off);
-                const unsigned r0 = (unsigned)__builtin_amdgcn_fmed3f(ceilf(flo), 0.0f, rwin);
-                const float2 *zq = zrs + r0;
-                const float *yq = yrow + r0;
+                // rows that miss the cell contribute exactly zero below.  The start
+                // r0 = clamp(ceil(flo), 0, nv - C) is formed negated, as
+                // -r0 = floor(clamp(-flo, -(nv - C), 0)): one floor-convert instead of
+                // a ceil, a clamp and a convert, and the same integer.  |r0| < 2^14,
+                // so both byte offsets are 24-bit products.
+                const float nflo = fmaf(-zk0[q], zk0[q] >= 0.0f ? iA2 : iA1, -fv_off);
+                const int m = (int)floorf(__builtin_amdgcn_fmed3f(nflo, nrwin, 0.0f));
+                const float2 *zq = (const float2 *)((const char *)zrs + __mul24(m, -8));
+                const float *yq = (const float *)((const char *)yrow + (uint32_t)__mul24(m, -4));
                 float a = acc[q];
 #pragma unroll
                 for (int c = 0; c < C; ++c) {
