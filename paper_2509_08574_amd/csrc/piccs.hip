@@ -83,12 +83,17 @@ k_weights(GeoK G, const float *__restrict__ x, const float *__restrict__ xp, flo
           float *__restrict__ w1, float *__restrict__ w2) {
     const VoxIdx v = vox_index(G);
     if (!v.ok) return;
-    const int64_t c = v.c, sy = (int64_t)G.nx * G.Z;
+    const int64_t c = v.c;
+    const bool hx_ = v.i < G.nx - 1, hy_ = v.j < G.ny - 1, hz_ = v.k < G.nz - 1;
+    // every read is issued unconditionally (offset 0 at the volume's far faces) and
+    // the face condition selects afterwards, so all reads are in flight at once
+    const int64_t ox = hx_ ? G.Z : 0, oy = hy_ ? (int64_t)G.nx * G.Z : 0, oz = hz_ ? 1 : 0;
     const float x0 = x[c], p0 = xp[c];
-    float gx = 0.f, gy = 0.f, gz = 0.f, hx = 0.f, hy = 0.f, hz = 0.f;
-    if (v.i < G.nx - 1) { gx = x0 - x[c + G.Z]; hx = gx - (p0 - xp[c + G.Z]); }
-    if (v.j < G.ny - 1) { gy = x0 - x[c + sy]; hy = gy - (p0 - xp[c + sy]); }
-    if (v.k < G.nz - 1) { gz = x0 - x[c + 1]; hz = gz - (p0 - xp[c + 1]); }
+    const float xx = x[c + ox], xy = x[c + oy], xz = x[c + oz];
+    const float px = xp[c + ox], py = xp[c + oy], pz = xp[c + oz];
+    const float gx = hx_ ? x0 - xx : 0.f, gy = hy_ ? x0 - xy : 0.f, gz = hz_ ? x0 - xz : 0.f;
+    const float hx = hx_ ? gx - (p0 - px) : 0.f, hy = hy_ ? gy - (p0 - py) : 0.f,
+                hz = hz_ ? gz - (p0 - pz) : 0.f;
     w1[c] = 1.0f / sqrtf(sqrtf(gx * gx + gy * gy + gz * gz) + tau2);
     w2[c] = 1.0f / sqrtf(sqrtf(hx * hx + hy * hy + hz * hz) + tau2);
 }
@@ -110,40 +115,45 @@ k_regF(GeoK G, const float *__restrict__ V, const float *__restrict__ Vp,
     const float s1 = (float)*s1p, s2 = (float)*s2p;
     double sum = 0.0;
     if (v.ok) {
-        const int64_t c = v.c, sy = (int64_t)G.nx * G.Z;
+        const int64_t c = v.c;
+        const bool hi[3] = {v.i < G.nx - 1, v.j < G.ny - 1, v.k < G.nz - 1};
+        const int64_t st[3] = {G.Z, (int64_t)G.nx * G.Z, 1};
+        // all reads are issued before any is used: neighbour offsets are 0 at the
+        // volume's far faces and the face condition selects afterwards; the old
+        // u values are read only when they are used (s2 != 0, uniform)
+        const bool keep = s2 != 0.0f;
         const float x0 = V[c];
-        float d[3] = {0.f, 0.f, 0.f}, e[3] = {0.f, 0.f, 0.f};
         const float p0 = HAS_VP ? Vp[c] : 0.f;
-        if (v.i < G.nx - 1) {
-            d[0] = x0 - V[c + G.Z];
-            e[0] = HAS_VP ? d[0] - (p0 - Vp[c + G.Z]) : d[0];
+        float xn[3], pn[3], o1[3], o2[3];
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            const int64_t o = hi[q] ? st[q] : 0;
+            xn[q] = V[c + o];
+            pn[q] = HAS_VP ? Vp[c + o] : 0.f;
+            o1[q] = keep ? u1[c + q * cstride] : 0.f;
+            o2[q] = (keep && !PIPLE) ? u2[c + q * cstride] : 0.f;
         }
-        if (v.j < G.ny - 1) {
-            d[1] = x0 - V[c + sy];
-            e[1] = HAS_VP ? d[1] - (p0 - Vp[c + sy]) : d[1];
-        }
-        if (v.k < G.nz - 1) {
-            d[2] = x0 - V[c + 1];
-            e[2] = HAS_VP ? d[2] - (p0 - Vp[c + 1]) : d[2];
-        }
+        const float o2p = (keep && PIPLE) ? u2[c] : 0.f;
         const float a1 = alpha * W1[c], a2 = PIPLE ? lam : lam * W2[c];
         float acc = 0.f;
 #pragma unroll
         for (int q = 0; q < 3; ++q) {
-            float n1 = s1 * (a1 * d[q]);
-            if (s2 != 0.0f) n1 = fmaf(s2, u1[c + q * cstride], n1);
+            const float d = hi[q] ? x0 - xn[q] : 0.f;
+            const float e = hi[q] ? (HAS_VP ? d - (p0 - pn[q]) : d) : 0.f;
+            float n1 = s1 * (a1 * d);
+            if (keep) n1 = fmaf(s2, o1[q], n1);
             u1[c + q * cstride] = n1;
             acc = fmaf(n1, n1, acc);
             if (!PIPLE) {
-                float n2 = s1 * (a2 * e[q]);
-                if (s2 != 0.0f) n2 = fmaf(s2, u2[c + q * cstride], n2);
+                float n2 = s1 * (a2 * e);
+                if (keep) n2 = fmaf(s2, o2[q], n2);
                 u2[c + q * cstride] = n2;
                 acc = fmaf(n2, n2, acc);
             }
         }
         if (PIPLE) {
             float n2 = s1 * (a2 * (x0 - p0));
-            if (s2 != 0.0f) n2 = fmaf(s2, u2[c], n2);
+            if (keep) n2 = fmaf(s2, o2p, n2);
             u2[c] = n2;
             acc = fmaf(n2, n2, acc);
         }
@@ -173,22 +183,36 @@ k_regA(GeoK G, const float *__restrict__ t, const float *__restrict__ W1,
         const int64_t st[3] = {G.Z, (int64_t)G.nx * G.Z, 1};
         const bool hi[3] = {v.i < G.nx - 1, v.j < G.ny - 1, v.k < G.nz - 1};
         const bool lo[3] = {v.i > 0, v.j > 0, v.k > 0};
-        const float w1c = W1[c];
+        // all reads are issued before any is used: the backward neighbour's offset is
+        // 0 at the volume's near faces and the face condition selects afterwards
+        const float w1c = W1[c], w2c = PIPLE ? 0.f : W2[c];
+        const float tc = t[c], vo = s2 != 0.0f ? V[c] : 0.f;
+        float a0[3], an[3], wn1[3], b0[3], bn[3], wn2[3];
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            const int64_t o = lo[q] ? st[q] : 0;
+            a0[q] = u1[q * cstride + c];
+            an[q] = u1[q * cstride + c - o];
+            wn1[q] = W1[c - o];
+            if (!PIPLE) {
+                b0[q] = u2[q * cstride + c];
+                bn[q] = u2[q * cstride + c - o];
+                wn2[q] = W2[c - o];
+            }
+        }
         float r1 = 0.f, r2 = 0.f;
 #pragma unroll
         for (int q = 0; q < 3; ++q) {
-            const float *a = u1 + q * cstride;
-            if (hi[q]) r1 += w1c * a[c];
-            if (lo[q]) r1 -= W1[c - st[q]] * a[c - st[q]];
+            if (hi[q]) r1 += w1c * a0[q];
+            if (lo[q]) r1 -= wn1[q] * an[q];
             if (!PIPLE) {
-                const float *b = u2 + q * cstride;
-                if (hi[q]) r2 += W2[c] * b[c];
-                if (lo[q]) r2 -= W2[c - st[q]] * b[c - st[q]];
+                if (hi[q]) r2 += w2c * b0[q];
+                if (lo[q]) r2 -= wn2[q] * bn[q];
             }
         }
         if (PIPLE) r2 = u2[c];
-        float vn = s1 * (t[c] + alpha * r1 + lam * r2);
-        if (s2 != 0.0f) vn = fmaf(s2, V[c], vn);
+        float vn = s1 * (tc + alpha * r1 + lam * r2);
+        if (s2 != 0.0f) vn = fmaf(s2, vo, vn);
         V[c] = vn;
         sum = (double)vn * (double)vn;
     }
