@@ -60,6 +60,11 @@ GEOMS = {
                     dso=40.0, dsd=70.0, n_views=7),
     "thin_x": dict(nx=1, ny=9, nz=7, vx=1.0, vy=1.0, vz=1.0, nu=13, nv=11, du=1.1, dv=1.1,
                    dso=40.0, dsd=70.0, n_views=7),
+    # the largest detector height accepted (16384 rows): the adjoint keeps one
+    # (rg, cz) pair per row in LDS, 128 KB.  Thin x-y cells keep the cone within
+    # one z plane per cell; rows far from the centre miss the volume
+    "max_nv": dict(nx=5, ny=4, nz=8, vx=0.01, vy=0.01, vz=1.0, nu=2, nv=16384, du=0.05,
+                   dv=0.5, dso=40.0, dsd=70.0, n_views=3),
     # columns taller than 512 cells: the adjoint splits each column over waves
     "tall": dict(nx=6, ny=5, nz=600, vx=0.2, vy=0.2, vz=0.2, nu=10, nv=300, du=0.4, dv=0.4,
                  dso=70.0, dsd=110.0, n_views=5),
