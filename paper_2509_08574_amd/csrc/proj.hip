@@ -4,8 +4,8 @@
 // read as exact ray/voxel chord lengths; Krylov solvers touch it only through
 // products with A and A^T (Sec. 2.2.2).  Chord arithmetic: chord.h.
 //
-// Forward (k_fwd): one wave per (view, detector column u, 64 or 128 detector
-// rows); each lane walks one or two rows.  All rays of one detector column
+// Forward (k_fwd): one wave per (view, detector column u, 64, 128 or 256
+// detector rows); each lane walks one, two or four rows.  All rays of one detector column
 // share their x-y path, so the wave walks the voxel columns (i, j) it crosses
 // in lock-step (uniform control flow) while every lane tracks its own z cell.
 // Volumes are stored column-major (z fastest), so at each step the lanes read a
@@ -233,7 +233,7 @@ struct FwdLane {
 // Walk the x-y segments of one detector column for RPL rows per lane moving in
 // z direction DIR.  Two segments per loop trip with alternating registers, so
 // the one-ahead reads never need to be copied (and waited for) early; with two
-// rows per lane the two walks share the segment stream and double the reads in
+// or four rows per lane the walks share the segment stream and multiply the reads in
 // flight.
 template <int DIR, int MODE, int RPL, int DT>
 __device__ __forceinline__ void fwd_walk(const GeoK &G, const void *vol, const int2 *sp,
@@ -292,9 +292,12 @@ __device__ __forceinline__ void fwd_walk(const GeoK &G, const void *vol, const i
     }
 }
 
-// Rows per lane of the forward kernel: two when each detector half has at
-// least 128 rows.
-__host__ __device__ inline int fwd_rpl(int nv) { return nv / 2 >= 128 ? 2 : 1; }
+// Rows per lane of the forward kernel: as many as each detector half fills
+// (four from 256 rows, two from 128).  Rows of one lane share the segment
+// stream's scalar work, which is what binds the walk.
+__host__ __device__ inline int fwd_rpl(int nv) {
+    return nv / 2 >= 256 ? 4 : nv / 2 >= 128 ? 2 : 1;
+}
 
 template <int MODE, int RPL, int DT>
 __global__ void __launch_bounds__(256)
@@ -405,7 +408,9 @@ static void launch_forward_rpl(const GeoK &G, int mode, const FwdArgs &a, hipStr
 template <int DT>
 static void launch_forward_dt(const GeoK &G, int mode, const FwdArgs &a, hipStream_t s,
                               dim3 grid) {
-    if (fwd_rpl(G.nv) == 2)
+    if (fwd_rpl(G.nv) == 4)
+        launch_forward_rpl<4, DT>(G, mode, a, s, grid);
+    else if (fwd_rpl(G.nv) == 2)
         launch_forward_rpl<2, DT>(G, mode, a, s, grid);
     else
         launch_forward_rpl<1, DT>(G, mode, a, s, grid);
