@@ -4,8 +4,8 @@
 // read as exact ray/voxel chord lengths; Krylov solvers touch it only through
 // products with A and A^T (Sec. 2.2.2).  Chord arithmetic: chord.h.
 //
-// Forward (k_fwd): one wave per (view, detector column u, 64, 128 or 256
-// detector rows); each lane walks one, two or four rows.  All rays of one detector column
+// Forward (k_fwd): one wave per (view, detector column u, 64 to 256 detector
+// rows); each lane walks one to four rows.  All rays of one detector column
 // share their x-y path, so the wave walks the voxel columns (i, j) it crosses
 // in lock-step (uniform control flow) while every lane tracks its own z cell.
 // Volumes are stored column-major (z fastest), so at each step the lanes read a
@@ -300,13 +300,15 @@ __host__ __device__ inline int fwd_padded_rows(int nv, int rpl) {
 }
 
 // Rows per lane of the forward kernel.  Rows of one lane share the segment
-// stream's scalar work, which co-limits the walk, so four rows per lane cost
-// about 6 % less per row than two; but their 256-row blocks can leave more lanes
-// idle.  Four when each half has 256 rows and that pads the detector by under
-// 5 % more rows than two do; two from 128 rows per half; else one.
+// stream's scalar work, which co-limits the walk, so more rows per lane cost
+// less per row (four against two: about 6 %); but larger blocks can leave lanes
+// idle.  The most rows per lane (4, 3, 2) whose blocks pad the detector by under
+// 5 % more rows than the tightest choice; one below 128 rows per half.
 __host__ __device__ inline int fwd_rpl(int nv) {
     if (nv / 2 < 128) return 1;
-    if (nv / 2 >= 256 && 20 * fwd_padded_rows(nv, 4) < 21 * fwd_padded_rows(nv, 2)) return 4;
+    const int best = min(fwd_padded_rows(nv, 2), fwd_padded_rows(nv, 3));
+    if (nv / 2 >= 256 && 20 * fwd_padded_rows(nv, 4) < 21 * best) return 4;
+    if (nv / 2 >= 192 && 20 * fwd_padded_rows(nv, 3) < 21 * fwd_padded_rows(nv, 2)) return 3;
     return 2;
 }
 
@@ -421,6 +423,8 @@ static void launch_forward_dt(const GeoK &G, int mode, const FwdArgs &a, hipStre
                               dim3 grid) {
     if (fwd_rpl(G.nv) == 4)
         launch_forward_rpl<4, DT>(G, mode, a, s, grid);
+    else if (fwd_rpl(G.nv) == 3)
+        launch_forward_rpl<3, DT>(G, mode, a, s, grid);
     else if (fwd_rpl(G.nv) == 2)
         launch_forward_rpl<2, DT>(G, mode, a, s, grid);
     else

@@ -68,6 +68,9 @@ GEOMS = {
     # 512 detector rows: the forward takes four rows per lane (256 per wave)
     "rows4": dict(nx=3, ny=3, nz=6, vx=1.0, vy=1.0, vz=1.0, nu=5, nv=512, du=2.0, dv=0.5,
                   dso=100.0, dsd=200.0, n_views=2, angles=[0.3, 2.0]),
+    # 384 detector rows: three rows per lane (192 per wave fill each half exactly)
+    "rows3": dict(nx=3, ny=3, nz=6, vx=1.0, vy=1.0, vz=1.0, nu=5, nv=384, du=2.0, dv=0.5,
+                  dso=100.0, dsd=200.0, n_views=2, angles=[0.7, 4.0]),
     # columns taller than 512 cells: the adjoint splits each column over waves
     "tall": dict(nx=6, ny=5, nz=600, vx=0.2, vy=0.2, vz=0.2, nu=10, nv=300, du=0.4, dv=0.4,
                  dso=70.0, dsd=110.0, n_views=5),
@@ -98,7 +101,7 @@ def test_forward_and_back_match_oracle(orc, lib, name):
 
 
 @pytest.mark.parametrize("name", ["odd", "slab", "one_view", "one_row", "one_col", "thin_x",
-                                  "rows4"])
+                                  "rows4", "rows3"])
 def test_gpu_pair_is_exact_transpose(orc, lib, name):
     """Dense A from unit volumes and dense A^T from unit projections agree bitwise."""
     import torch
