@@ -247,6 +247,9 @@ def serving_bench(args, cbct, synth, np, torch, dev):
                 if k >= args.serve_warmup:
                     # late submission adds to the latency
                     lat.append(info["t_done"] - info["t_submit"] + (t_sub - arr))
+                    if len(lat) % 100 == 0:
+                        log(f"[serve] rho {rho}: {len(lat)} of {args.serve_requests} requests "
+                            f"done ({time.perf_counter() - t0:.0f}s)")
             time.sleep(2e-4)
         wall = time.perf_counter() - t0
         st = srv.stats()
