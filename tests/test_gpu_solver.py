@@ -135,6 +135,27 @@ def test_odd_geometry_solve(orc, lib):
     assert rel(xg, ref.x) <= SOLVE_TOL
 
 
+@pytest.mark.parametrize("nv, dv", [(300, 0.7), (384, 0.55), (512, 0.5)])
+def test_solve_with_several_rows_per_lane(orc, lib, nv, dv):
+    """Detector heights at which the forward projector takes two, three and four
+    rows per lane (its solver form fuses the u update and the |u|^2 partials);
+    a tall volume puts data on every row.  FP32 and mixed BF16."""
+    rng = np.random.default_rng(nv)
+    d = dict(nx=10, ny=10, nz=100, vx=1.0, vy=1.0, vz=1.0, nu=12, nv=nv, du=2.0, dv=dv,
+             dso=100.0, dsd=200.0, n_views=12)
+    og = orc.Geometry.from_dict(d)
+    xp = rng.uniform(size=og.vol_shape).astype(np.float32).astype(np.float64)
+    xt = xp + 0.3 * (rng.uniform(size=og.vol_shape) > 0.9)
+    b = orc.forward(og, xt).astype(np.float32).astype(np.float64)
+    ref = orc.irn_piccs(og, b, xp, xp, 0.5, 1.5, 0.2, 2, 4)
+    xg, rep = _gpu_solve(lib, d, b, xp, xp, lib.SolveParams(0.5, 1.5, 0.2, 2, 4))
+    assert rep["inner_done"] == 8
+    assert rel(xg, ref.x) <= SOLVE_TOL
+    xm, _ = _gpu_solve(lib, d, b, xp, xp,
+                       lib.SolveParams(0.5, 1.5, 0.2, 2, 4, precision=lib.PREC_MIXED_BF16))
+    assert rel(xm, ref.x) <= 1e-3
+
+
 @pytest.mark.parametrize("prec", ["bf16", "f16"])
 def test_mixed_precision_solve_within_1e3_of_fp64(orc, lib, prec):
     """16-bit projector operand, fp32 accumulation, fp64 Krylov scalars: <= 1e-3 vs FP64."""
