@@ -475,7 +475,7 @@ constexpr int kBackTileW = CBCT_BACK_TILE_W, kBackTileH = CBCT_BACK_TILE_H;
 template <int C>
 __global__ void __launch_bounds__(256)
 k_back(GeoK G, const float *__restrict__ yhat, float *__restrict__ out, const int *brk,
-       float a_ref, float z_lo_mm, int kspan, int nq) {
+       float a_ref, float z_lo_mm, float fv_off, float fu_margin, int kspan, int nq) {
     if (brk && *brk == 2) return;
     extern __shared__ float lds[];
     float2 *zrs = (float2 *)lds;  // per-row (rg, cz)
@@ -521,9 +521,9 @@ k_back(GeoK G, const float *__restrict__ yhat, float *__restrict__ out, const in
     const float xlo = (fi - 0.5f * G.nx) * G.hx, xhi = xlo + G.hx;
     const float ylo = (fj - 0.5f * G.ny) * G.hy, yhi = ylo + G.hy;
     const float fu_scale = G.dsd / G.du, fu_off = 0.5f * G.nu - 0.5f;
-    // row index of height z at ray parameter A: z / (A dv) + nv/2 - 1/2; the
-    // 1e-3 margin (rows) is folded into the offset
-    const float a_ref_dv = a_ref * G.dv, fv_off = 0.5f * G.nv - 0.5f - 1e-3f;
+    // row index of height z at ray parameter A: z / (A dv) + nv/2 - 1/2; fv_off
+    // is nv/2 - 1/2 less the window's safety margin (rows), formed on the host
+    const float a_ref_dv = a_ref * G.dv;
     const float nrwin = -(float)(G.nv - C);  // minus the last allowed window start
 
     // The detector footprint of the column is the same for every lane: once per
@@ -535,8 +535,8 @@ k_back(GeoK G, const float *__restrict__ yhat, float *__restrict__ out, const in
         if (tv == 0) {
             // detector u range of the column's x-y square: a ray with a positive
             // chord crosses the square's interior, so its pixel lies strictly between
-            // the extreme corner images (the small margin covers the approximate
-            // reciprocal)
+            // the extreme corner images (fu_margin columns cover the approximate
+            // reciprocal and the rounding of the column positions)
             const int vw = view + lane;
             fu0v = 0;
             fu1v = -1;
@@ -553,8 +553,8 @@ k_back(GeoK G, const float *__restrict__ yhat, float *__restrict__ out, const in
                     umin = fminf(umin, fu);
                     umax = fmaxf(umax, fu);
                 }
-                fu0v = max(0, (int)ceilf(umin - 1e-3f));
-                fu1v = min(G.nu - 1, (int)floorf(umax + 1e-3f));
+                fu0v = max(0, (int)ceilf(umin - fu_margin));
+                fu1v = min(G.nu - 1, (int)floorf(umax + fu_margin));
             }
         }
         const int iu0 = __builtin_amdgcn_readlane(fu0v, tv);
@@ -612,9 +612,24 @@ k_back(GeoK G, const float *__restrict__ yhat, float *__restrict__ out, const in
     if (zs == nzs - 1 && lane == 0) oc[G.nz + 1] = 0.0f;
 }
 
+// Safety margin (rows) by which a window starts before the first row whose
+// centre can meet the cell.  It covers the float32 rounding of the window
+// start, which grows with the row position: the row offset nv/2 - 1/2 and the
+// start itself are rounded to half an ulp each (an ulp of a position below nv
+// is at most nv * 2^-23 rows), and the approximate reciprocal adds up to one
+// ulp of the distance from the centre row (below nv/2 rows); plus the table
+// rounding of the rows' plane parameters, a small fraction of 1e-3 rows.  The
+// margin is 1e-3 rows plus eight ulps' worth of nv * 2^-23.
+static double back_margin_rows(int nv) { return 1e-3 + 8.0 * nv * std::ldexp(1.0, -23); }
+// The same margin for the detector columns visited per view, whose corner
+// images carry the same kinds of rounding at positions below nu.
+static double back_margin_cols(int nu) { return 1e-3 + 8.0 * nu * std::ldexp(1.0, -23); }
+
 // Upper bound on the number of detector rows that can meet one cell within one
 // column interval: rows span (z_k / A1 .. z_k+1 / A2) with A the absolute ray
-// parameter, so the span is at most (hz / A_min + R_z (A_max - A_min) / A_min^2) / dv.
+// parameter, so the span is at most (hz / A_min + R_z (A_max - A_min) / A_min^2) / dv;
+// a window starting the margin early must reach that far, and 2 % plus 0.01 rows
+// cover the rounding of the bound.
 static int back_candidates(const GeoK &G) {
     const double hx = G.nx * (double)G.hx / 2, hy = G.ny * (double)G.hy / 2;
     const double rxy = std::sqrt(hx * hx + hy * hy);
@@ -623,7 +638,7 @@ static int back_candidates(const GeoK &G) {
     const double diag = std::sqrt((double)G.hx * G.hx + (double)G.hy * G.hy);
     const double dA = diag / G.dsd;  // parameter extent of one column interval
     const double rz = G.nz * (double)G.hz / 2;
-    const double span = (G.hz / amin + rz * dA / (amin * amin)) / G.dv;
+    const double span = (G.hz / amin + rz * dA / (amin * amin)) / G.dv + back_margin_rows(G.nv);
     return (int)std::floor(span * 1.02 + 0.01) + 1;
 }
 
@@ -640,11 +655,13 @@ void launch_back(const GeoK &G, const float *yhat, float *out, const int *brk, h
     const size_t shm = sizeof(float2) * (size_t)G.nv;
     const float a_ref = G.dso / G.dsd;
     const float z_lo_mm = -0.5f * G.nz * G.hz;
+    const float fv_off = (float)(0.5 * G.nv - 0.5 - back_margin_rows(G.nv));
+    const float fu_margin = (float)back_margin_cols(G.nu);
     // window of C rows; never more rows than the detector has
     const int C = std::min(back_candidates(G), G.nv);
     auto go = [&](auto kern) {
         hipLaunchKernelGGL(kern, dim3((unsigned)nb), dim3(256), shm, s, G, yhat, out, brk, a_ref,
-                           z_lo_mm, kspan, nq);
+                           z_lo_mm, fv_off, fu_margin, kspan, nq);
     };
     switch (C) {
         case 1: go(k_back<1>); break;

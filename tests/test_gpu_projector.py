@@ -170,12 +170,25 @@ def _sample_rays(g, rng, n):
     return np.array(rays, dtype=np.int64)
 
 
-def _sample_voxels(g, rng, n):
+def _sample_voxels(g, rng, n, n_edge=0):
+    """n uniform voxels; the bottom, middle and top z slices of the corner, edge
+    and centre columns; and n_edge voxels drawn near the volume's z extremes and
+    x-y corners (where the adjoint's candidate windows and detector ranges meet
+    their clamps)."""
     vox = list(rng.integers(0, g.nx * g.ny * g.nz, n))
-    for k in (0, g.nz // 2, g.nz - 1):
-        for j in (0, g.ny - 1):
-            for i in (0, g.nx // 2, g.nx - 1):
-                vox.append((k * g.ny + j) * g.nx + i)
+    ks = sorted({0, 1, g.nz // 2 - 1, g.nz // 2, g.nz - 2, g.nz - 1})
+    cols = [(i, j) for i in (0, g.nx // 2, g.nx - 1) for j in (0, g.ny // 2, g.ny - 1)]
+    for k in ks:
+        for (i, j) in cols:
+            vox.append((k * g.ny + j) * g.nx + i)
+    for _ in range(n_edge):
+        k = int(rng.integers(0, 4))
+        k = k if rng.integers(2) else g.nz - 1 - k
+        i = int(rng.integers(0, 8))
+        i = i if rng.integers(2) else g.nx - 1 - i
+        j = int(rng.integers(0, 8))
+        j = j if rng.integers(2) else g.ny - 1 - j
+        vox.append((k * g.ny + j) * g.nx + i)
     return np.array(vox, dtype=np.int64)
 
 
@@ -196,9 +209,27 @@ def test_full_size_sampled_parity(orc, lib, cfg):
     del xd, yg
     y = rng.uniform(size=og.proj_shape).astype(np.float32)
     xg = lib.back(gg, dev(y)).view(-1)
-    vox = _sample_voxels(og, rng, 40 if cfg == "c2" else 12)
+    # at least 200 voxels at every size, a third of them at the z extremes and corners
+    vox = _sample_voxels(og, rng, 80, n_edge=80)
+    assert vox.size >= 200
     xo = orc.back_voxels(og, y.astype(np.float64), vox)
     assert rel(xg[torch.from_numpy(vox).cuda()].double().cpu().numpy(), xo) <= TOL
+
+
+def test_far_rows_dot_product(lib):
+    """A tall volume on the tallest detector (16384 rows): the adjoint's windows
+    sit about 6700 rows from the centre row, where the window margin grows with
+    the row position.  <A x, y> = <x, A^T y> within float32 summation."""
+    d = dict(nx=4, ny=4, nz=3200, vx=0.5, vy=0.5, vz=1.0, nu=8, nv=16384, du=0.5, dv=0.4,
+             dso=3000.0, dsd=5000.0, n_views=16)
+    gg = lib.Geometry.from_dict(d)
+    rng = np.random.default_rng(8)
+    x = rng.uniform(size=gg.vol_shape)
+    y = rng.uniform(size=gg.proj_shape)
+    lhs = float(np.vdot(host(lib.forward(gg, dev(x))), y.astype(np.float32)))
+    rhs = float(np.vdot(x.astype(np.float32), host(lib.back(gg, dev(y)))))
+    assert lhs > 0
+    assert abs(lhs - rhs) <= 1e-6 * abs(lhs)
 
 
 def test_dtype_inputs(orc, lib):
@@ -212,6 +243,15 @@ def test_dtype_inputs(orc, lib):
         xr = xs.float().cpu().numpy().astype(np.float64) * 0.5
         yg = host(lib.forward(gg, xs, x_scale=0.5))
         assert rel(yg, orc.forward(og, xr)) <= TOL
+    # the adjoint's 16-bit input: the same, for A^T of projections stored in bf16 / fp16
+    for name in ("odd", "rows"):
+        og, gg = _geoms(orc, lib, name)
+        y = rng.uniform(size=og.proj_shape)
+        for dt in (torch.bfloat16, torch.float16):
+            ys = torch.from_numpy(y).to(dt).cuda()
+            yr = ys.float().cpu().numpy().astype(np.float64) * 2.0
+            xg = host(lib.back(gg, ys, y_scale=2.0))
+            assert rel(xg, orc.back(og, yr)) <= TOL
 
 
 def test_deterministic(lib):

@@ -1,0 +1,140 @@
+"""IRN-PICCS solve parity against the FP64 oracle at benchmark scale.
+
+The oracle is slow at these sizes (one product of A and A^T at 256^3 / 90 views
+is about 7 G chords each way), so the iteration counts are reduced and stated;
+the geometry, the kernels' launch shapes, the partial-sum arrays (e.g. 23 040
+forward partials at 256^3, past the reduction's 8192-entry unrolled threshold)
+and the solver epilogues are those of the benchmarked workloads:
+
+* 256^3 at 1 mm, 512 x 512 detector at 0.8 mm, 90 views: 2 reweightings x 2 LSQR
+  iterations (six products with restarts);
+* the 512 x 512 x 400 volume at 0.4 mm with the 1024 x 1024 detector at 0.3 mm,
+  12 of its 180 views (every 15th): 1 reweighting x 2 LSQR iterations.
+
+Each precision form is compared with the same oracle result (paper Sec. 2.2.2:
+LSQR on the augmented system; reading R25: relative L2 of the final x against
+the oracle's final x after the same iterations): FP32 storage within 1e-4
+(float32 rounding through a short Krylov recurrence), the mixed BF16 / scaled
+FP16 forms within 1e-3 (the precision bar).  The phi-bar histories are compared
+with the same tolerances.  Inputs are float32-rounded on both sides.
+"""
+import time
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp32": 1e-4, "mixed_bf16": 1e-3, "mixed_f16": 1e-3}
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2509_08574_amd import cbct
+    return cbct
+
+
+def _prec(lib, name):
+    return {"fp32": lib.PREC_FP32, "mixed_bf16": lib.PREC_MIXED_BF16,
+            "mixed_f16": lib.PREC_MIXED_F16}[name]
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def _counting(orc, og, tag):
+    """The oracle's A and A^T, printing one progress line per product."""
+    n = {"A": 0, "AT": 0}
+    t0 = time.time()
+
+    def A(x):
+        n["A"] += 1
+        print(f"[{tag}] oracle A #{n['A']} ({time.time() - t0:.0f}s)", flush=True)
+        return orc.forward(og, x)
+
+    def AT(y):
+        n["AT"] += 1
+        print(f"[{tag}] oracle A^T #{n['AT']} ({time.time() - t0:.0f}s)", flush=True)
+        return orc.back(og, y)
+    return A, AT
+
+
+def _case(orc, name):
+    from paper_2509_08574_amd import synth
+    if name == "c2":
+        d = synth.geometry("c2")
+        sp = synth.SOLVE_PARAMS["c2"]
+        prior, cur = synth.c2_case(sp["seed"])
+        n_outer, n_inner = 2, 2
+    else:
+        d = synth.geometry("c5")
+        sp = synth.SOLVE_PARAMS["c5"]
+        base, centre, axis = synth.c5_case(sp["seed"])
+        cur = base.copy()
+        cur.reshape(-1)[synth.c5_scan(base, centre, axis, 1)] = 2.0
+        prior = base
+        ang = 2.0 * np.pi * np.arange(d["n_views"]) / d["n_views"]
+        d = dict(d, n_views=12, angles=list(ang[::15]))
+        n_outer, n_inner = 1, 2
+    og = orc.Geometry.from_dict(d)
+    t = time.time()
+    b = synth.noisy_line_integrals(orc.forward(og, cur), sp["I0"], seed=sp["seed"] + 200)
+    b = b.astype(np.float32).astype(np.float64)
+    prior = prior.astype(np.float32).astype(np.float64)
+    print(f"[{name}] oracle b in {time.time() - t:.0f}s", flush=True)
+    A, AT = _counting(orc, og, name)
+    t = time.time()
+    ref = orc.irn_piccs(og, b, prior, prior, sp["alpha"], sp["lam"], sp["tau"], n_outer,
+                        n_inner, A=A, AT=AT)
+    print(f"[{name}] oracle IRN-PICCS {n_outer}x{n_inner} in {time.time() - t:.0f}s",
+          flush=True)
+    return dict(d=d, b=b, prior=prior, sp=sp, n_outer=n_outer, n_inner=n_inner, ref=ref)
+
+
+@pytest.fixture(scope="module")
+def cases(orc):
+    return {}
+
+
+def _get(cases, orc, name):
+    if name not in cases:
+        cases[name] = _case(orc, name)
+    return cases[name]
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("name", ["c2", "c5_12views"])
+@pytest.mark.parametrize("form", ["fp32", "mixed_bf16", "mixed_f16"])
+def test_full_size_solve_matches_fp64_oracle(orc, lib, cases, name, form):
+    import torch
+    c = _get(cases, orc, "c2" if name == "c2" else "c5")
+    sp = c["sp"]
+    print(f"[{name}] GPU IRN-PICCS {c['n_outer']}x{c['n_inner']} {form}", flush=True)
+    g = lib.Geometry.from_dict(c["d"])
+    b = torch.from_numpy(c["b"].astype(np.float32)).cuda()
+    xp = torch.from_numpy(c["prior"].astype(np.float32)).cuda()
+    x = xp.clone()
+    p = lib.SolveParams(sp["alpha"], sp["lam"], sp["tau"], c["n_outer"], c["n_inner"],
+                        precision=_prec(lib, form))
+    x, rep = lib.solve(g, b, xp, x, p)
+    xg = x.cpu().numpy().astype(np.float64)
+    ref = c["ref"]
+    err = _rel(xg, ref.x)
+    print(f"[{name}] {form}: rel L2 vs FP64 oracle {err:.3e}; phi-bar GPU {rep['phibar']} "
+          f"oracle {ref.phibar}", flush=True)
+    assert rep["inner_done"] == len(ref.phibar) == c["n_outer"] * c["n_inner"]
+    assert rep["outer_done"] == c["n_outer"] and rep["breakdown"] == 0
+    assert err <= TOL[form]
+    np.testing.assert_allclose(rep["phibar"], ref.phibar, rtol=TOL[form])
+    # the solve moved from its start by more than the tolerance, and the update
+    # x - x_0 itself matches within ten times the tolerance (so the comparison is
+    # not of x_0 with itself)
+    moved = _rel(ref.x, c["prior"])
+    upd = float(np.linalg.norm(xg - ref.x) / np.linalg.norm(ref.x - c["prior"]))
+    print(f"[{name}] {form}: |x - x0| / |x| = {moved:.3e}, update error {upd:.3e}", flush=True)
+    assert moved > TOL[form]
+    assert upd <= 10 * TOL[form]
