@@ -115,6 +115,31 @@ int cbct_forward(const cbct_geom *g, const void *x, cbct_dtype xt, float x_scale
 int cbct_back(const cbct_geom *g, const void *y, cbct_dtype yt, float y_scale, float *x,
               void *hip_stream);
 
+/*
+ * Allocation-free cbct_forward, for callers that cannot allocate device memory:
+ * code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc.  Same operation, arguments, layouts and results as cbct_forward
+ * (bit for bit: the same kernels), but its temporaries -- the padded column copy
+ * of x (4 bytes per cell for CBCT_F32, 2 for BF16 / F16, pads and guards
+ * included: (nz + 2) * nx * ny + 128 cells) and the column-layout projections
+ * (4 * N bytes), each rounded up to 256 bytes -- live in one fixed device array
+ * of the library of CBCT_FORWARD_NOALLOC_MAX_BYTES bytes per device.  That
+ * array is placed on a device the first time this call runs there and is held
+ * until the process ends.  The call allocates and frees nothing.
+ * Preconditions: the geometry's tables must already be on the current device
+ * (any earlier cbct_forward, cbct_back, solve or FDK call with g on this device
+ * placed them), and the temporaries must fit the array; otherwise the call
+ * returns CBCT_ERR_INVALID (with a message) before enqueueing anything.
+ * Every call on one device shares that device's array and leaves its contents
+ * behind: calls that overlap on one device (different streams, or threads
+ * without stream ordering between them) race and must not be issued.
+ * Errors: CBCT_ERR_INVALID (null pointer, bad dtype/scale, size, tables not on
+ * the device), CBCT_ERR_DEVICE.
+ */
+#define CBCT_FORWARD_NOALLOC_MAX_BYTES ((size_t)256 << 20)
+int cbct_forward_noalloc(const cbct_geom *g, const void *x, cbct_dtype xt, float x_scale,
+                         float *y, void *hip_stream);
+
 /* ------------------------------------------------------------------------ */
 /* Column layout (the kernels' native layout)                                */
 /*

@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 LIB = os.path.join(HERE, "libcbct.so")
-SOURCES = ["geom.cpp", "proj.hip", "piccs.hip", "server.cpp", "fdk.hip"]
+SOURCES = ["geom.cpp", "proj.hip", "piccs.hip", "server.cpp", "fdk.hip", "noalloc.hip"]
 ARCH = os.environ.get("CBCT_OFFLOAD_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

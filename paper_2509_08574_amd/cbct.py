@@ -34,7 +34,7 @@ EXPORTS = ["cbct_last_error", "cbct_geom_create", "cbct_geom_destroy", "cbct_geo
            "cbct_cols_to_vol", "cbct_proj_to_cols", "cbct_cols_to_proj", "cbct_forward_cols",
            "cbct_back_cols", "cbct_server_create", "cbct_server_add_prior", "cbct_server_submit",
            "cbct_server_poll", "cbct_server_stats_get", "cbct_server_destroy",
-           "cbct_server_footprint", "cbct_fdk"]
+           "cbct_server_footprint", "cbct_fdk", "cbct_forward_noalloc"]
 
 
 class GeomDesc(ctypes.Structure):
@@ -71,6 +71,8 @@ _lib.cbct_geom_sizes.argtypes = [_vp, ctypes.POINTER(ctypes.c_int64),
 _lib.cbct_geom_nnz.argtypes = [_vp, ctypes.POINTER(ctypes.c_int64), _vp]
 _lib.cbct_forward.argtypes = [_vp, _vp, ctypes.c_int, ctypes.c_float, _vp, _vp]
 _lib.cbct_back.argtypes = [_vp, _vp, ctypes.c_int, ctypes.c_float, _vp, _vp]
+_lib.cbct_forward_noalloc.argtypes = [_vp, _vp, ctypes.c_int, ctypes.c_float, _vp, _vp]
+FORWARD_NOALLOC_MAX_BYTES = 256 << 20  # CBCT_FORWARD_NOALLOC_MAX_BYTES
 _lib.piccs_weights.argtypes = [_vp, _vp, _vp, ctypes.c_double, _vp, _vp, _vp]
 _lib.piccs_workspace_bytes.argtypes = [_vp, ctypes.POINTER(Params),
                                        ctypes.POINTER(ctypes.c_size_t)]
@@ -189,6 +191,17 @@ def forward(g: Geometry, x: torch.Tensor, y: torch.Tensor | None = None, x_scale
     _need(y, g.proj_shape)
     _check(_lib.cbct_forward(g.handle, _ptr(x), _DT[x.dtype], float(x_scale), _ptr(y),
                              _stream(stream)))
+    return y
+
+
+def forward_noalloc(g: Geometry, x: torch.Tensor, y: torch.Tensor, x_scale=1.0,
+                    stream=None) -> torch.Tensor:
+    """y = A x (cbct_forward_noalloc: the library's fixed scratch array, no
+    allocation; the geometry must already have been used on this device)."""
+    _need(x, g.vol_shape, tuple(_DT))
+    _need(y, g.proj_shape)
+    _check(_lib.cbct_forward_noalloc(g.handle, _ptr(x), _DT[x.dtype], float(x_scale), _ptr(y),
+                                     _stream(stream)))
     return y
 
 

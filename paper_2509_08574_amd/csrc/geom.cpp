@@ -247,6 +247,16 @@ GeoK geo_for_device(cbct_geom *g) {
     return make_geok(g, t);
 }
 
+bool geo_if_placed(cbct_geom *g, GeoK *out) {
+    int dev = 0;
+    CBCT_HIP(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lk(g->mu);
+    auto it = g->dev.find(dev);
+    if (it == g->dev.end()) return false;
+    *out = make_geok(g, it->second);
+    return true;
+}
+
 void geo_place(cbct_geom *g, void *mem, hipStream_t s) {
     CBCT_REQUIRE(mem && ((uintptr_t)mem & 255) == 0, "table memory must be 256-byte aligned");
     int dev = 0;

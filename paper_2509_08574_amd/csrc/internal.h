@@ -185,4 +185,15 @@ void cols_to_vol(const GeoK &G, const float *cols, float *x, hipStream_t s);
 void proj_to_cols(const GeoK &G, const float *y, float *ycol, bool scale_by_L, hipStream_t s);
 void cols_to_proj(const GeoK &G, const float *ycol, float *y, hipStream_t s);
 
+// y = A x from an API-layout volume of storage type xt (value = stored * x_scale)
+// into API-layout projections y, through the column layouts held in caller
+// temporaries: cols (forward_api_bytes' cols_bytes, 4-byte aligned) and ycol.
+void forward_api_bytes(const cbct_geom *g, cbct_dtype xt, size_t *cols_bytes,
+                       size_t *ycol_bytes);
+void forward_api(const GeoK &G, const cbct_geom *g, const void *x, cbct_dtype xt,
+                 float x_scale, float *y, void *cols, float *ycol, hipStream_t s);
+// Kernel arguments for g on the current device if its tables are already there
+// (never allocates); false otherwise.
+bool geo_if_placed(cbct_geom *g, GeoK *out);
+
 }  // namespace cbct

@@ -789,6 +789,38 @@ static void to_f32(const void *in, cbct_dtype dt, float scale, float *out, int64
     CBCT_HIP(hipGetLastError());
 }
 
+// ---------------------------------------------------------------- API-layout forward
+
+void forward_api_bytes(const cbct_geom *g, cbct_dtype xt, size_t *cols_bytes,
+                       size_t *ycol_bytes) {
+    const size_t es = xt == CBCT_F32 ? 4 : 2;
+    *cols_bytes = es * (size_t)g->pad_floats();
+    *ycol_bytes = sizeof(float) * (size_t)g->n_proj();
+}
+
+void forward_api(const GeoK &G, const cbct_geom *g, const void *x, cbct_dtype xt,
+                 float x_scale, float *y, void *cols, float *ycol, hipStream_t s) {
+    size_t cols_bytes = 0, ycol_bytes = 0;
+    forward_api_bytes(g, xt, &cols_bytes, &ycol_bytes);
+    // padded column copy in the input's own storage type (pads and guards zero);
+    // the kernel widens 16-bit values on load and applies x_scale in its epilogue
+    launch_fill((float *)cols, (int64_t)(cols_bytes / 4), 0.0f, s);
+    FwdArgs a{};
+    if (xt == CBCT_F32) {
+        float *P = (float *)cols + kGuard;
+        vol_to_cols(G, (const float *)x, P, s);
+        a.vol = P;
+    } else {
+        unsigned short *P = (unsigned short *)cols + kGuard;
+        vol_to_cols16(G, (const unsigned short *)x, P, s);
+        a.vol = P;
+    }
+    a.out = ycol;
+    a.scale = x_scale;
+    launch_forward(G, FWD_PLAIN, a, s, xt);
+    cols_to_proj(G, ycol, y, s);
+}
+
 }  // namespace cbct
 
 using namespace cbct;
@@ -837,27 +869,11 @@ int cbct_forward(const cbct_geom *gc, const void *x, cbct_dtype xt, float x_scal
         cbct_geom *g = const_cast<cbct_geom *>(gc);
         hipStream_t s = (hipStream_t)hip_stream;
         GeoK G = geo_for_device(g);
-        const int64_t N = g->n_proj();
-        const size_t es = xt == CBCT_F32 ? 4 : 2;
-        // padded column copy in the input's own storage type; the kernel widens
-        // 16-bit values on load and applies x_scale in its epilogue
-        StreamBuf cols(es * (size_t)g->pad_floats(), s);
-        StreamBuf ycol(sizeof(float) * N, s);
-        launch_fill(cols.f(), (int64_t)(es * (size_t)g->pad_floats() / 4), 0.0f, s);
-        FwdArgs a{};
-        if (xt == CBCT_F32) {
-            float *P = cols.f() + kGuard;
-            vol_to_cols(G, (const float *)x, P, s);
-            a.vol = P;
-        } else {
-            unsigned short *P = (unsigned short *)cols.p + kGuard;
-            vol_to_cols16(G, (const unsigned short *)x, P, s);
-            a.vol = P;
-        }
-        a.out = ycol.f();
-        a.scale = x_scale;
-        launch_forward(G, FWD_PLAIN, a, s, xt);
-        cols_to_proj(G, ycol.f(), y, s);
+        size_t cols_bytes = 0, ycol_bytes = 0;
+        forward_api_bytes(g, xt, &cols_bytes, &ycol_bytes);
+        StreamBuf cols(cols_bytes, s);
+        StreamBuf ycol(ycol_bytes, s);
+        forward_api(G, g, x, xt, x_scale, y, cols.p, ycol.f(), s);
         return CBCT_OK;
     } catch (const std::exception &e) {
         return translate(e);
