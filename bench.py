@@ -1,18 +1,25 @@
 """Benchmark of the MI355X IRN-PICCS hot path.
 
 One step = one full IRN-PICCS reconstruction (weights, augmented LSQR with the
-projector pair, stencils, device-side recurrences) of the 256^3 / 90-view /
-512x512-detector workload: 5 reweightings x 10 LSQR iterations, float32, warm-
-started from the prior.  Inputs are seeded synthetic phantoms resident in HBM
-before the timed region.
+projector pair, stencils, device-side FP64 recurrences) of one scan of the
+repeated-scan sequence: a 512 x 512 x 400 volume at 0.4 mm, 180 views on a
+1024 x 1024 detector at 0.3 mm, 4 reweightings x 10 LSQR iterations.  Ten
+successive scans carry a needle advancing 3 mm per scan; each scan starts from
+the previous reconstruction, which stays on the device (scans cycle 1..10).
+Float32 storage and projector arithmetic, float64 Krylov scalars.  The same
+sequence is then run in the mixed BF16 form.  Inputs are seeded synthetic
+phantoms and noisy projections resident in HBM before the timed region.
 
 Printed: ONE JSON line.  ``value`` is the whole-job voxel-projection rate of
 the reconstruction: (A and A^T applications in a step) x nx*ny*nz*n_views /
-step time.  Extra fields report the isolated A and A^T rates, the roofline of
-the dominant projector kernel (timed with HIP events on the stream it runs
-on) and the FP64 CPU oracle timed on this host on a bounded sample.
+step time.  Extra fields: the 256^3 / 90-view case in all three precision
+forms, each form's error against the FP64 oracle (on reduced problems the
+oracle finishes in seconds, labelled as such), the isolated A and A^T rates,
+the roofline of the dominant projector kernel (timed with HIP events on the
+stream it runs on), the serving stream, and the FP64 CPU oracle timed on this
+host on a bounded sample.
 
-Usage: python bench.py [--gpus 1] [--steps 3] [--warmup 1] [--workload c2]
+Usage: python bench.py [--gpus 1] [--steps 3] [--warmup 1]
 """
 import argparse
 import json
@@ -24,6 +31,12 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# VALU issue capacity: 256 CUs x 4 SIMDs, one issue cycle each per clock at 2.4 GHz.
+# A wave64 instruction occupies its SIMD for 2 cycles (full-rate float32 add / mul
+# / fma, 32-bit integer add, bitwise ops), 4 cycles (min / max / med3, conversions,
+# 24-bit multiplies, VOP3 selects and shifts) or 8 cycles (reciprocal), as the
+# issue-rate probe measures on the device.
+SIMD_ISSUE_PEAK_CYCLES_S = 256 * 4 * 2.4e9
 
 
 def log(*a):
@@ -31,8 +44,8 @@ def log(*a):
 
 
 PROFILES = os.path.join(ROOT, "profiles")
-# sources that define the projector kernels: a recorded HBM traffic figure is
-# only used while these are byte-identical to what was profiled
+# sources that define the projector kernels: a recorded figure is only used
+# while these are byte-identical to what was profiled
 KERNEL_SOURCES = ("paper_2509_08574_amd/csrc/proj.hip", "paper_2509_08574_amd/csrc/chord.h",
                   "paper_2509_08574_amd/csrc/internal.h")
 
@@ -47,10 +60,10 @@ def kernel_source_hash():
 
 
 def recorded_profile(kernel, workload, key):
-    """A per-launch figure (`traffic_bytes_per_launch`: FETCH_SIZE + WRITE_SIZE,
-    calibrated; `valu_wave_instructions_per_launch`: SQ_INSTS_VALU) from the
-    committed rocprofv3 summary of `kernel` on `workload`, or None if there is
-    none or the kernel sources changed since it was taken."""
+    """A per-launch figure from the committed rocprofv3 summary of `kernel` on
+    `workload` (profiles/<kernel>_<workload>.md, section "Recorded for
+    bench.py"), or None if there is none or the kernel sources changed since it
+    was taken."""
     path = os.path.join(PROFILES, f"{kernel}_{workload}.md")
     if not os.path.exists(path):
         return None
@@ -68,73 +81,362 @@ def recorded_profile(kernel, workload, key):
         return None
 
 
-def recorded_traffic(kernel, workload):
-    return recorded_profile(kernel, workload, "traffic_bytes_per_launch")
+def time_op(torch, stream, fn, reps):
+    """Average duration (ms) of fn() over `reps` back-to-back launches, HIP
+    events recorded on `stream` (the stream fn launches its kernel on)."""
+    fn()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    for _ in range(reps):
+        fn()
+    ev1.record(stream)
+    ev1.synchronize()
+    return ev0.elapsed_time(ev1) / reps
 
 
-# One wave64 FP32 VALU instruction per SIMD per 4 cycles: 256 CUs x 4 SIMDs x 2.4 GHz / 4.
-VALU_PEAK_WAVE_INSTR_S = 256 * 4 * 2.4e9 / 4
-
-
-def projector_roofline(args, cbct, torch, g, xc, ywc, stream):
-    """Event-timed isolated A and A^T (column layout, on `stream`) and the
-    operand-bytes roofline of the slower one."""
+def projector_pair(args, cbct, torch, g, xc, ywc, stream, workload):
+    """Event-timed isolated A and A^T (column layout, on `stream`), and the
+    roofline object of the slower one (the dominant kernel of a solve)."""
     M, N = g.sizes()
     V = g.proj_shape[0]
     yc = torch.empty_like(ywc)
     xo = torch.empty_like(xc)
-
-    def time_op(fn, reps):
-        fn()
-        ev0 = torch.cuda.Event(enable_timing=True)
-        ev1 = torch.cuda.Event(enable_timing=True)
-        ev0.record(stream)
-        for _ in range(reps):
-            fn()
-        ev1.record(stream)
-        ev1.synchronize()
-        return ev0.elapsed_time(ev1) / reps
-
-    t_fwd = time_op(lambda: cbct.forward_cols(g, xc, yc, stream=stream), args.op_reps)
-    t_back = time_op(lambda: cbct.back_cols(g, ywc, xo, stream=stream), args.op_reps)
+    t_fwd = time_op(torch, stream, lambda: cbct.forward_cols(g, xc, yc, stream=stream),
+                    args.op_reps)
+    t_back = time_op(torch, stream, lambda: cbct.back_cols(g, ywc, xo, stream=stream),
+                     args.op_reps)
     nnz = g.nnz()
-    bytes_fwd = 4.0 * nnz + 4.0 * N
-    bytes_back = 4.0 * nnz + 4.0 * M
     gvp_fwd = M * V / (t_fwd * 1e-3) / 1e9
     gvp_back = M * V / (t_back * 1e-3) / 1e9
-    dom = ("k_back", t_back, bytes_back) if t_back >= t_fwd else ("k_fwd", t_fwd, bytes_fwd)
-    achieved = dom[2] / (dom[1] * 1e-3) / 1e9
-    log(f"[bench] A {t_fwd:.3f} ms ({gvp_fwd:.1f} Gvp/s), A^T {t_back:.3f} ms "
+    log(f"[bench] {workload}: A {t_fwd:.3f} ms ({gvp_fwd:.1f} Gvp/s), A^T {t_back:.3f} ms "
         f"({gvp_back:.1f} Gvp/s), nnz {nnz}")
-    traffic = recorded_traffic(dom[0], args.workload)
-    roofline = {"bound": "hbm", "kernel": dom[0], "achieved": round(achieved, 1),
-                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": traffic, "avg_launch_ms": round(dom[1], 4),
-                "algorithmic_bytes_per_launch": dom[2], "units_per_launch": nnz,
-                "unit_bytes": "4 B per chord + 4 B per output element",
-                "traffic_source": f"profiles/{dom[0]}_{args.workload}.md" if traffic else None}
-    valu = recorded_profile(dom[0], args.workload, "valu_wave_instructions_per_launch")
-    if valu:
-        # what binds the projectors: VALU issue (recorded instruction count over
-        # this run's launch time, against the nominal issue peak)
-        rate = valu / (dom[1] * 1e-3)
-        roofline["valu"] = {"bound": "alu", "achieved": round(rate / 1e9, 1),
-                            "peak": VALU_PEAK_WAVE_INSTR_S / 1e9,
-                            "unit": "G wave-instructions/s",
-                            "frac": round(rate / VALU_PEAK_WAVE_INSTR_S, 4),
-                            "instructions_per_launch": valu}
-    # which resource binds: the operand-bytes figure above is not the HBM traffic
-    # (most operands come from L2); beside it, the measured utilisations
-    ta = recorded_profile(dom[0], args.workload, "ta_busy_fraction")
-    td = recorded_profile(dom[0], args.workload, "td_busy_fraction")
-    l2 = recorded_profile(dom[0], args.workload, "l2_hit_rate")
-    if traffic and ta is not None and td is not None:
-        util = {"hbm_traffic": round(traffic / (dom[1] * 1e-3) / 1e9 / HBM_PEAK_GBS, 3),
-                "valu_issue": roofline["valu"]["frac"] if "valu" in roofline else None,
-                "texture_address": ta, "texture_data": td}
-        roofline["measured"] = dict(util, l2_hit_rate=l2)
-        roofline["binds"] = [k for k, v in util.items() if v is not None and v >= 0.85]
-    return t_fwd, t_back, nnz, gvp_fwd, gvp_back, roofline
+    out = {"A_ms": round(t_fwd, 4), "AT_ms": round(t_back, 4),
+           "A_gvoxel_proj_s": round(gvp_fwd, 2), "AT_gvoxel_proj_s": round(gvp_back, 2),
+           "nnz": nnz}
+    dom = ("k_back", t_back, 4.0 * nnz + 4.0 * M) if t_back >= t_fwd else \
+          ("k_fwd", t_fwd, 4.0 * nnz + 4.0 * N)
+    return out, roofline(dom, nnz, workload)
+
+
+def roofline(dom, nnz, workload):
+    """Roofline of the dominant projector kernel.
+
+    Both projectors are gathers whose operands come mostly from L2 and L1, so
+    their HBM traffic is far below what they consume (`effective_GBps` is the
+    operand-bytes rate, 4 B per chord, which exceeds the HBM peak).  What binds
+    them is instruction issue: the VALU issue cycles the kernel's instructions
+    occupy, over the chip's issue capacity.  `achieved` is that per-launch
+    demand (recorded from the committed profile of the same sources) over this
+    run's event-timed launch."""
+    kernel, t_ms, opbytes = dom
+    cyc = recorded_profile(kernel, workload, "valu_issue_cycles_per_launch")
+    traffic = recorded_profile(kernel, workload, "traffic_bytes_per_launch")
+    r = {"bound": "alu", "kernel": kernel, "achieved": None,
+         "peak": round(SIMD_ISSUE_PEAK_CYCLES_S / 1e9, 1),
+         "unit": "G VALU issue cycles/s (SIMD-cycles)", "frac": None, "traffic": traffic,
+         "avg_launch_ms": round(t_ms, 4), "units_per_launch": nnz, "unit_name": "chord",
+         "valu_issue_cycles_per_launch": cyc,
+         "effective_GBps": round(opbytes / (t_ms * 1e-3) / 1e9, 1),
+         "profile": f"profiles/{kernel}_{workload}.md"}
+    if cyc:
+        ach = cyc / (t_ms * 1e-3)
+        r["achieved"] = round(ach / 1e9, 1)
+        r["frac"] = round(ach / SIMD_ISSUE_PEAK_CYCLES_S, 4)
+    if traffic:
+        r["hbm"] = {"achieved_GBps": round(traffic / (t_ms * 1e-3) / 1e9, 1),
+                    "peak_GBps": HBM_PEAK_GBS,
+                    "frac": round(traffic / (t_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+    for key, name in (("td_busy_fraction", "texture_data_busy"),
+                      ("ta_busy_fraction", "texture_address_busy"),
+                      ("l2_hit_rate", "l2_hit_rate")):
+        v = recorded_profile(kernel, workload, key)
+        if v is not None:
+            r.setdefault("measured", {})[name] = v
+    return r
+
+
+def noisy_b(torch, synth, y, I0, seed, dev):
+    """Poisson counts at I0 exp(-mu p), clamped >= 1, back to line integrals
+    (seeded, on the device)."""
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(seed)
+    lam = I0 * torch.exp(-synth.MU_WATER_PER_MM * y.double())
+    counts = torch.clamp(torch.poisson(lam, generator=gen), min=1.0)
+    return (-torch.log(counts / I0) / synth.MU_WATER_PER_MM).float()
+
+
+def repeated_scans(args, cbct, synth, np, torch, dev, stream):
+    """The headline workload: the ten-scan 512 x 512 x 400 sequence, FP32 then
+    mixed BF16, each started from x_p at scan 1 and warm-started from the
+    previous reconstruction at every later step."""
+    gd = synth.geometry("c5")
+    sp = synth.SOLVE_PARAMS["c5"]
+    t = time.time()
+    base, centre, axis = synth.c5_case(sp["seed"])
+    log(f"[bench] phantom 512x512x400 in {time.time() - t:.1f}s")
+    g = cbct.Geometry.from_dict(gd)
+    M, N = g.sizes()
+    V = gd["n_views"]
+    xp = torch.from_numpy(base.astype(np.float32)).to(dev)
+    needles, bs = [], []
+    for s_ in range(1, 11):
+        idx = torch.from_numpy(synth.c5_scan(base, centre, axis, s_)).to(dev)
+        cur = xp.clone()
+        cur.view(-1)[idx] = 2.0
+        bs.append(noisy_b(torch, synth, cbct.forward(g, cur), sp["I0"], 500 + s_, dev))
+        needles.append(idx)
+        del cur
+    torch.cuda.synchronize()
+    log(f"[bench] 10 scans ready ({time.time() - t:.1f}s)")
+
+    def truth(scan):
+        cur = xp.clone()
+        cur.view(-1)[needles[scan]] = 2.0
+        return cur
+
+    products = sp["n_outer"] * (sp["n_inner"] + 1)
+    vox_proj_step = 2.0 * products * M * V
+    forms, xs = {}, {}
+    for name, pr in (("fp32", cbct.PREC_FP32), ("mixed_bf16", cbct.PREC_MIXED_BF16)):
+        if name != "fp32" and args.fp32_only:
+            continue
+        p = cbct.SolveParams(sp["alpha"], sp["lam"], sp["tau"], sp["n_outer"], sp["n_inner"],
+                             precision=pr)
+        ws = cbct.alloc_workspace(g, p, device=dev)
+        x = xp.clone()
+
+        def step(i):
+            cbct.solve(g, bs[i % 10], xp, x, p, workspace=ws, report=False)
+
+        for i in range(args.warmup):
+            step(i)
+        torch.cuda.synchronize()
+        step_ms = []
+        t0 = time.perf_counter()
+        for i in range(args.warmup, args.warmup + args.steps):
+            ts = time.perf_counter()
+            step(i)
+            torch.cuda.synchronize()
+            step_ms.append(1e3 * (time.perf_counter() - ts))
+        torch.cuda.synchronize()
+        total = time.perf_counter() - t0
+        last = (args.warmup + args.steps - 1) % 10
+        tr = truth(last)
+        err = float(torch.linalg.norm(x - tr) / torch.linalg.norm(tr))
+        err_prior = float(torch.linalg.norm(xp - tr) / torch.linalg.norm(tr))
+        forms[name] = {"s_per_recon": round(total / args.steps, 4),
+                       "step_ms_p50": round(float(np.percentile(step_ms, 50)), 2),
+                       "step_ms_max": round(float(max(step_ms)), 2),
+                       "value_gvoxel_proj_s": round(vox_proj_step * args.steps / total / 1e9, 3),
+                       "last_scan": last + 1, "rel_err_vs_truth": round(err, 5),
+                       "rel_err_prior_vs_truth": round(err_prior, 5)}
+        xs[name] = x
+        log(f"[bench] 512x512x400 {name}: {args.steps} steps, {1e3 * total / args.steps:.1f} "
+            f"ms/recon; scan {last + 1}: rel err vs truth {err:.4f} (prior {err_prior:.4f})")
+        del ws, tr
+    if "mixed_bf16" in forms:
+        f32, bf = forms["fp32"], forms["mixed_bf16"]
+        bf["speedup_vs_fp32"] = round(f32["s_per_recon"] / bf["s_per_recon"], 3)
+        bf["rel_l2_vs_fp32_gpu"] = float(torch.linalg.norm(xs["mixed_bf16"] - xs["fp32"])
+                                         / torch.linalg.norm(xs["fp32"]))
+    forms["fp32"]["speedup_vs_fp32"] = 1.0
+    del xs
+    # isolated projectors on this workload (column layout, HIP events on this stream)
+    xc = cbct.vol_to_cols(g, truth(0))
+    ywc = cbct.proj_to_cols(g, bs[0], weighted=True)
+    ops, roof = projector_pair(args, cbct, torch, g, xc, ywc, stream, "c5")
+    del xc, ywc, bs
+    g.close()
+    return dict(gd=gd, sp=sp, M=M, V=V, products=products, vox_proj_step=vox_proj_step,
+                forms=forms, ops=ops, roofline=roof, base=base, centre=centre, axis=axis)
+
+
+def c2_case_forms(args, cbct, synth, np, torch, dev, stream):
+    """The 256^3 / 90-view / 512^2 workload (5 x 10, prior from a 720-view plain
+    LSQR reconstruction): FP32 and both mixed forms, FDK, isolated projectors."""
+    gd = synth.geometry("c2")
+    sp = synth.SOLVE_PARAMS["c2"]
+    g = cbct.Geometry.from_dict(gd)
+    M, N = g.sizes()
+    V = gd["n_views"]
+    base, cur = synth.c2_case(sp["seed"])
+    cur_d = torch.from_numpy(cur.astype(np.float32)).to(dev)
+    base_d = torch.from_numpy(base.astype(np.float32)).to(dev)
+    gp = cbct.Geometry.from_dict(synth.geometry("c2_prior"))
+    bp = cbct.forward(gp, base_d)
+    xprior = torch.zeros_like(base_d)
+    cbct.solve(gp, bp, xprior, xprior, cbct.SolveParams(0.0, 0.0, sp["tau"], 1, 30), report=False)
+    del bp
+    gp.close()
+    y = cbct.forward(g, cur_d)
+    b = synth.noisy_line_integrals(y.cpu().numpy(), sp["I0"], seed=sp["seed"] + 100)
+    b_d = torch.from_numpy(b.astype(np.float32)).to(dev)
+    products = sp["n_outer"] * (sp["n_inner"] + 1)
+    out, ref = {}, None
+    for name, pr in (("fp32", cbct.PREC_FP32), ("mixed_bf16", cbct.PREC_MIXED_BF16),
+                     ("mixed_f16", cbct.PREC_MIXED_F16)):
+        p = cbct.SolveParams(sp["alpha"], sp["lam"], sp["tau"], sp["n_outer"], sp["n_inner"],
+                             precision=pr)
+        ws = cbct.alloc_workspace(g, p, device=dev)
+        x = xprior.clone()
+        cbct.solve(g, b_d, xprior, x, p, workspace=ws, report=False)
+        torch.cuda.synchronize()
+        reps = max(1, args.c2_steps)
+        t = time.perf_counter()
+        for _ in range(reps):
+            x.copy_(xprior)
+            cbct.solve(g, b_d, xprior, x, p, workspace=ws, report=False)
+        torch.cuda.synchronize()
+        sec = (time.perf_counter() - t) / reps
+        if ref is None:
+            ref = x.clone()
+        out[name] = {"s_per_recon": round(sec, 4),
+                     "gvoxel_proj_s": round(2.0 * products * M * V / sec / 1e9, 2),
+                     "rel_err_vs_truth": round(float(torch.linalg.norm(x - cur_d)
+                                                     / torch.linalg.norm(cur_d)), 5),
+                     "rel_l2_vs_fp32_gpu": float(torch.linalg.norm(x - ref)
+                                                 / torch.linalg.norm(ref))}
+        del ws
+        log(f"[bench] 256^3 {name}: {sec * 1e3:.1f} ms/recon")
+    for k in out:
+        out[k]["speedup_vs_fp32"] = round(out["fp32"]["s_per_recon"] / out[k]["s_per_recon"], 3)
+    out["rel_err_prior_vs_truth"] = round(float(torch.linalg.norm(xprior - cur_d)
+                                                / torch.linalg.norm(cur_d)), 5)
+    # FDK of the same scan (direct method, no prior)
+    xf = cbct.fdk(g, b_d, stream=stream)
+    out["fdk_ms"] = round(time_op(torch, stream, lambda: cbct.fdk(g, b_d, xf, stream=stream),
+                                  args.op_reps), 3)
+    out["rel_err_fdk_vs_truth"] = round(float(torch.linalg.norm(xf - cur_d)
+                                              / torch.linalg.norm(cur_d)), 5)
+    del xf
+    xc = cbct.vol_to_cols(g, cur_d)
+    ywc = cbct.proj_to_cols(g, b_d, weighted=True)
+    ops, roof = projector_pair(args, cbct, torch, g, xc, ywc, stream, "c2")
+    out.update(ops)
+    out["roofline"] = roof
+    out["workload"] = ("256x256x256 volume at 1 mm, 90 views, 512x512 detector at 0.8 mm, "
+                       "IRN-PICCS 5x10, prior from a 720-view plain LSQR reconstruction")
+    g.close()
+    return out
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def cpu_baseline_and_oracle_errors(args, cbct, synth, np, torch, dev, c5):
+    """The FP64 oracle on this host: (1) its A and A^T on a bounded sample of the
+    headline workload (4 of the 180 views, all host threads) and on one view of
+    the 256^3 workload with one thread (per-core rate); (2) every precision form
+    against the oracle's IRN-PICCS on reduced problems it finishes in seconds to
+    a minute: the full 64^3 / 48-view solve (3 x 5), and the headline volume and
+    detector with 4 of its 180 views (1 x 2)."""
+    from oracle import oracle as orc
+    nthreads = orc.num_threads()
+    gd, sp = c5["gd"], c5["sp"]
+    V = gd["n_views"]
+    nvs = 4
+    ang = 2.0 * np.pi * np.arange(V) / V
+    sub = dict(gd, n_views=nvs, angles=list(ang[::V // nvs][:nvs]))
+    og = orc.Geometry.from_dict(sub)
+    cur = c5["base"].copy()
+    cur.reshape(-1)[synth.c5_scan(c5["base"], c5["centre"], c5["axis"], 1)] = 2.0
+    t = time.perf_counter()
+    y_or = orc.forward(og, cur)
+    t_A = (time.perf_counter() - t) * V / nvs
+    t = time.perf_counter()
+    orc.back(og, y_or)
+    t_AT = (time.perf_counter() - t) * V / nvs
+    M = c5["M"]
+    rate = 2.0 * M * V / (t_A + t_AT) / 1e9
+    log(f"[bench] oracle, {nthreads} threads: A {t_A:.1f}s, A^T {t_AT:.1f}s per full "
+        f"512x512x400 / 180-view application (from {nvs} views)")
+    errs = {}
+    # (a) the full 64^3 / 48-view solve
+    gd1 = synth.geometry("c1")
+    sp1 = synth.SOLVE_PARAMS["c1"]
+    og1 = orc.Geometry.from_dict(gd1)
+    prior1, cur1 = synth.c1_case()
+    b1 = synth.noisy_line_integrals(orc.forward(og1, cur1), sp1["I0"], seed=101)
+    b1 = b1.astype(np.float32).astype(np.float64)
+    prior1 = prior1.astype(np.float32).astype(np.float64)
+    t = time.perf_counter()
+    ref1 = orc.irn_piccs(og1, b1, prior1, prior1, sp1["alpha"], sp1["lam"], sp1["tau"],
+                         sp1["n_outer"], sp1["n_inner"])
+    t_or1 = round(time.perf_counter() - t, 2)
+    # (b) the headline volume and detector, 4 views, 1 x 2
+    b5 = synth.noisy_line_integrals(y_or, sp["I0"], seed=sp["seed"] + 300)
+    b5 = b5.astype(np.float32).astype(np.float64)
+    prior5 = c5["base"].astype(np.float32).astype(np.float64)
+    t = time.perf_counter()
+    n_ops = [0]
+
+    def progress(fn):
+        def op(v):
+            n_ops[0] += 1
+            log(f"[bench] oracle 512x512x400 / 4 views: product {n_ops[0]} "
+                f"({time.perf_counter() - t:.0f}s)")
+            return fn(og, v)
+        return op
+    ref5 = orc.irn_piccs(og, b5, prior5, prior5, sp["alpha"], sp["lam"], sp["tau"], 1, 2,
+                         A=progress(orc.forward), AT=progress(orc.back))
+    t_or5 = round(time.perf_counter() - t, 2)
+    log(f"[bench] oracle IRN-PICCS: 64^3 3x5 in {t_or1}s, 512x512x400 4 views 1x2 in {t_or5}s")
+    cases = (("c1_64cubed_48views_3x5", gd1, b1, prior1, sp1, sp1["n_outer"], sp1["n_inner"],
+              ref1),
+             ("c5_geometry_4views_1x2", sub, b5, prior5, sp, 1, 2, ref5))
+    for label, gdx, bx, px, spx, no, ni, ref in cases:
+        gx = cbct.Geometry.from_dict(gdx)
+        bd = torch.from_numpy(bx.astype(np.float32)).to(dev)
+        pd = torch.from_numpy(px.astype(np.float32)).to(dev)
+        for name, pr in (("fp32", cbct.PREC_FP32), ("mixed_bf16", cbct.PREC_MIXED_BF16),
+                         ("mixed_f16", cbct.PREC_MIXED_F16)):
+            x = pd.clone()
+            cbct.solve(gx, bd, pd, x, cbct.SolveParams(spx["alpha"], spx["lam"], spx["tau"], no,
+                                                     ni, precision=pr), report=False)
+            xg = x.cpu().numpy().astype(np.float64)
+            errs.setdefault(name, {})[label] = float(np.linalg.norm(xg - ref.x)
+                                                     / np.linalg.norm(ref.x))
+        gx.close()
+        del bd, pd
+    cpu_extra = {"oracle_c1_solve_s": t_or1, "oracle_c5_4views_1x2_solve_s": t_or5}
+    # one thread, one view of the 256^3 workload
+    g2 = synth.geometry("c2")
+    og1 = orc.Geometry.from_dict(dict(g2, n_views=1, angles=[0.0]))
+    x2 = np.random.default_rng(9).uniform(size=og1.vol_shape)
+    t = time.perf_counter()
+    y1 = orc.forward(og1, x2, nthreads=1)
+    t1_A = time.perf_counter() - t
+    t = time.perf_counter()
+    orc.back(og1, y1, nthreads=1)
+    t1_AT = time.perf_counter() - t
+    # the oracle keeps the thread count it was last given: restore all threads
+    orc.back(orc.Geometry.from_dict(dict(g2, nx=4, ny=4, nz=4, n_views=1, angles=[0.0])),
+             np.zeros((1, g2["nv"], g2["nu"])), nthreads=nthreads)
+    m2 = g2["nx"] * g2["ny"] * g2["nz"]
+    per_core = 2.0 * m2 / (t1_A + t1_AT) / 1e9
+    log(f"[bench] oracle, 1 thread, one 256^3 view: A {t1_A:.2f}s, A^T {t1_AT:.2f}s")
+    cpu = {"value": round(rate, 4), "unit": "Gvoxel-proj/s", "cores": nthreads, "kind": "oracle",
+           "sample": f"FP64 A and A^T of {nvs} of the 180 views of the 512x512x400 / 1024^2 "
+                     f"workload, {nthreads} host threads, scaled to all views",
+           "A_s": round(t_A, 2), "AT_s": round(t_AT, 2),
+           "s_per_recon_extrapolated": round(c5["products"] * (t_A + t_AT), 1),
+           "per_core": {"value": round(per_core, 5), "unit": "Gvoxel-proj/s",
+                        "sample": "FP64 A and A^T of one view of the 256^3 / 512^2 workload, "
+                                  "one thread", "A_s": round(t1_A, 3), "AT_s": round(t1_AT, 3)},
+           "cpu_model": cpu_model(), "nproc": os.cpu_count(),
+           "omp_num_threads": os.environ.get("OMP_NUM_THREADS")}
+
+    cpu.update(cpu_extra)
+    return cpu, errs
 
 
 def serving_bench(args, cbct, synth, np, torch, dev):
@@ -459,10 +761,10 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="c2", choices=["c1", "c2"])
-    ap.add_argument("--prior", default="720", choices=["720", "truth"],
-                    help="prior image: 720-view plain-LSQR reconstruction, or the true base object")
+    ap.add_argument("--c2-steps", type=int, default=3,
+                    help="timed solves per precision form of the 256^3 case")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--no-c2", action="store_true", help="skip the 256^3 case")
     ap.add_argument("--fp32-only", action="store_true", help="skip the mixed-precision forms")
     ap.add_argument("--op-reps", type=int, default=10)
     ap.add_argument("--calib-copy-mib", type=int, default=0,
@@ -477,13 +779,16 @@ def main():
                     help="only the ten-scan 512x512x400 repeated sequence through the server")
     ap.add_argument("--ops-only", action="store_true",
                     help="time only the projector pair on random data (profiler passes)")
+    ap.add_argument("--workload", default="c5", choices=["c1", "c2", "c5"],
+                    help="geometry of --ops-only")
     ap.add_argument("--serve-only", action="store_true",
                     help="run only the serving stream and print its JSON")
-    ap.add_argument("--serve-requests", type=int, default=100,
+    ap.add_argument("--serve-requests", type=int, default=80,
                     help="measured requests per arrival rate")
     ap.add_argument("--serve-warmup", type=int, default=10)
     ap.add_argument("--serve-rho", type=lambda s: [float(v) for v in s.split(",")],
-                    default=[0.7], help="arrival rates as fractions of capacity, e.g. 0.5,0.7,0.9")
+                    default=[0.5, 0.9],
+                    help="arrival rates as fractions of capacity, e.g. 0.5,0.7,0.9")
     ap.add_argument("--serve-pool", type=int, default=24)
     ap.add_argument("--serve-slots", type=int, default=2)
     ap.add_argument("--serve-budget-gib", type=int, default=64)
@@ -501,26 +806,25 @@ def main():
     torch.cuda.set_device(0)
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream()
+    if args.calib_copy_mib > 0:
+        n = args.calib_copy_mib * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     if args.ops_only:
         # the projector pair alone on random data of the workload's shape
         # (their cost does not depend on the values); for profiler passes
         gq = cbct.Geometry.from_dict(synth.geometry(args.workload))
-        if args.calib_copy_mib > 0:
-            n = args.calib_copy_mib * (1 << 20) // 4
-            src = torch.ones(n, dtype=torch.float32, device=dev)
-            dst = torch.empty_like(src)
-            dst.copy_(src)
-            torch.cuda.synchronize()
-            del src, dst
         vf, voff, pf = cbct.col_sizes(gq)
         gen = torch.Generator(device=dev)
         gen.manual_seed(7)
         xc = torch.rand(vf, generator=gen, device=dev)
         ywc = torch.rand(pf, generator=gen, device=dev)
         xc = cbct.vol_to_cols(gq, cbct.cols_to_vol(gq, xc))     # zero pads and guards
-        r = projector_roofline(args, cbct, torch, gq, xc, ywc, stream)
-        print(json.dumps({"A_ms": r[0], "AT_ms": r[1], "nnz": r[2], "roofline": r[5]}),
-              flush=True)
+        ops, roof = projector_pair(args, cbct, torch, gq, xc, ywc, stream, args.workload)
+        print(json.dumps(dict(ops, roofline=roof)), flush=True)
         return
     if args.serve_only:
         print(json.dumps({"serving": serving_bench(args, cbct, synth, np, torch, dev)}),
@@ -538,212 +842,53 @@ def main():
         print(json.dumps({"quality": quality_bench(args, cbct, synth, np, torch, dev)}),
               flush=True)
         return
-    wl = args.workload
-    gd = synth.geometry(wl)
-    sp = synth.SOLVE_PARAMS[wl]
-    g = cbct.Geometry.from_dict(gd)
-    M, N = g.sizes()
-    V = gd["n_views"]
 
-    if args.calib_copy_mib > 0:
-        n = args.calib_copy_mib * (1 << 20) // 4
-        src = torch.ones(n, dtype=torch.float32, device=dev)
-        dst = torch.empty_like(src)
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
+    c5 = repeated_scans(args, cbct, synth, np, torch, dev, stream)
+    f32 = c5["forms"]["fp32"]
+    c2 = None if args.no_c2 else c2_case_forms(args, cbct, synth, np, torch, dev, stream)
+    cpu, errs = (None, {}) if args.no_cpu else cpu_baseline_and_oracle_errors(
+        args, cbct, synth, np, torch, dev, c5)
+    forms = c5["forms"]
+    for name, e in errs.items():
+        if name in forms:
+            forms[name]["rel_l2_vs_fp64_oracle"] = e
+    serving = None if args.no_serve else serving_bench(args, cbct, synth, np, torch, dev)
 
-    # ---------------- inputs (not timed)
-    t0 = time.time()
-    if wl == "c2":
-        base, cur = synth.c2_case(sp["seed"])
-    else:
-        base, cur = synth.c1_case(sp["seed"])
-    log(f"[bench] phantom {gd['nx']}x{gd['ny']}x{gd['nz']} in {time.time() - t0:.1f}s")
-    cur_d = torch.from_numpy(cur.astype(np.float32)).to(dev)
-    base_d = torch.from_numpy(base.astype(np.float32)).to(dev)
-    if wl == "c2" and args.prior == "720":
-        # prior: plain LSQR (alpha = lambda = 0), 30 iterations, noise-free 720-view scan
-        gp = cbct.Geometry.from_dict(synth.geometry("c2_prior"))
-        bp = cbct.forward(gp, base_d)
-        xprior = torch.zeros_like(base_d)
-        t0 = time.time()
-        cbct.solve(gp, bp, xprior, xprior, cbct.SolveParams(0.0, 0.0, sp["tau"], 1, 30),
-                   report=False)
-        torch.cuda.synchronize()
-        log(f"[bench] 720-view prior reconstruction in {time.time() - t0:.1f}s")
-        del bp
-        gp.close()
-    else:
-        xprior = base_d.clone()
-    y = cbct.forward(g, cur_d)
-    b = synth.noisy_line_integrals(y.cpu().numpy(), sp["I0"], seed=sp["seed"] + 100)
-    b_d = torch.from_numpy(b.astype(np.float32)).to(dev)
-    p = cbct.SolveParams(sp["alpha"], sp["lam"], sp["tau"], sp["n_outer"], sp["n_inner"])
-    ws = cbct.alloc_workspace(g, p, device=dev)
-    x = torch.empty_like(xprior)
-    products = p.n_outer * (p.n_inner + 1)
-    vox_proj_step = 2.0 * products * M * V
-
-    # ---------------- timed steps
-    for _ in range(args.warmup):
-        x.copy_(xprior)
-        cbct.solve(g, b_d, xprior, x, p, workspace=ws, report=False)
-    torch.cuda.synchronize()
-    log(f"[bench] warmup {args.warmup} done")
-    step_ms = []
-    torch.cuda.synchronize()
-    t_start = time.perf_counter()
-    for _ in range(args.steps):
-        ts = time.perf_counter()
-        x.copy_(xprior)
-        cbct.solve(g, b_d, xprior, x, p, workspace=ws, report=False)
-        torch.cuda.synchronize()
-        step_ms.append(1e3 * (time.perf_counter() - ts))
-    torch.cuda.synchronize()
-    total = time.perf_counter() - t_start
-    ms_per_step = 1e3 * total / args.steps
-    value = vox_proj_step * args.steps / total / 1e9
-    err_truth = float(torch.linalg.norm(x - cur_d) / torch.linalg.norm(cur_d))
-    err_prior = float(torch.linalg.norm(xprior - cur_d) / torch.linalg.norm(cur_d))
-    log(f"[bench] {args.steps} steps: {ms_per_step:.1f} ms/recon; rel err vs truth "
-        f"{err_truth:.4f} (prior {err_prior:.4f})")
-
-    # ---------------- precision forms: s/recon at this workload
-    forms = {}
-    if not args.fp32_only:
-        for name, pr in (("mixed_bf16", cbct.PREC_MIXED_BF16), ("mixed_f16", cbct.PREC_MIXED_F16)):
-            pm = cbct.SolveParams(sp["alpha"], sp["lam"], sp["tau"], sp["n_outer"],
-                                  sp["n_inner"], precision=pr)
-            wsm = cbct.alloc_workspace(g, pm, device=dev)
-            xm = torch.empty_like(xprior)
-            xm.copy_(xprior)
-            cbct.solve(g, b_d, xprior, xm, pm, workspace=wsm, report=False)
-            torch.cuda.synchronize()
-            t = time.perf_counter()
-            for _ in range(args.steps):
-                xm.copy_(xprior)
-                cbct.solve(g, b_d, xprior, xm, pm, workspace=wsm, report=False)
-            torch.cuda.synchronize()
-            sec = (time.perf_counter() - t) / args.steps
-            forms[name] = {"s_per_recon": round(sec, 4),
-                           "speedup_vs_fp32": round(ms_per_step / 1e3 / sec, 3),
-                           "rel_l2_vs_fp32_gpu": float(torch.linalg.norm(xm - x)
-                                                       / torch.linalg.norm(x))}
-            del wsm
-            log(f"[bench] {name}: {sec * 1e3:.1f} ms/recon")
-    forms["fp32"] = {"s_per_recon": round(ms_per_step / 1e3, 4), "speedup_vs_fp32": 1.0}
-
-    # ---------------- FDK of the same scan (direct method, no prior)
-    xf = cbct.fdk(g, b_d, stream=stream)
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    ev0.record(stream)
-    for _ in range(args.op_reps):
-        cbct.fdk(g, b_d, xf, stream=stream)
-    ev1.record(stream)
-    ev1.synchronize()
-    fdk_ms = ev0.elapsed_time(ev1) / args.op_reps
-    err_fdk = float(torch.linalg.norm(xf - cur_d) / torch.linalg.norm(cur_d))
-    log(f"[bench] FDK {fdk_ms:.2f} ms, rel err vs truth {err_fdk:.4f}")
-    del xf
-
-    # ---------------- isolated projector kernels (HIP events on this stream)
-    xc = cbct.vol_to_cols(g, cur_d)
-    ywc = cbct.proj_to_cols(g, b_d, weighted=True)
-    t_fwd, t_back, nnz, gvp_fwd, gvp_back, roofline = projector_roofline(
-        args, cbct, torch, g, xc, ywc, stream)
-
-    # ---------------- CPU oracle baseline (bounded sample)
-    cpu = None
-    if not args.no_cpu:
-        from oracle import oracle as orc
-        nthreads = orc.num_threads()
-        # the oracle's own full A and A^T on the first `nvs` views of the same scan
-        nvs = max(1, min(V, 12 if wl == "c2" else V))
-        ang = 2.0 * np.pi * np.arange(V) / V
-        og = orc.Geometry.from_dict(dict(gd, n_views=nvs, angles=ang[:nvs]))
-        xr = cur.astype(np.float64)
-        yr = b.astype(np.float64).reshape(V, gd["nv"], gd["nu"])[:nvs]
-        t = time.perf_counter()
-        orc.forward(og, xr)
-        t_A = (time.perf_counter() - t) * V / nvs
-        t = time.perf_counter()
-        orc.back(og, yr)
-        t_AT = (time.perf_counter() - t) * V / nvs
-        cpu_rate = 2.0 * M * V / (t_A + t_AT) / 1e9
-        cpu = {"value": round(cpu_rate, 4), "unit": "Gvoxel-proj/s", "cores": nthreads,
-               "kind": "oracle",
-               "sample": f"full FP64 A and A^T of {nvs} of the {V} views of {wl}, "
-                         f"{nthreads} host threads, scaled to all views",
-               "A_s": round(t_A, 2), "AT_s": round(t_AT, 2),
-               "s_per_recon_extrapolated": round(products * (t_A + t_AT), 1)}
-        log(f"[bench] oracle: A {t_A:.1f}s, A^T {t_AT:.1f}s per full application")
-
-        # every precision form against the FP64 oracle on the full 64^3 / 48-view
-        # solve (3 x 5 iterations), which the oracle finishes in seconds
-        gd1 = synth.geometry("c1")
-        sp1 = synth.SOLVE_PARAMS["c1"]
-        og1 = orc.Geometry.from_dict(gd1)
-        prior1, cur1 = synth.c1_case()
-        b1 = synth.noisy_line_integrals(orc.forward(og1, cur1), sp1["I0"], seed=101)
-        b1 = b1.astype(np.float32).astype(np.float64)
-        prior1 = prior1.astype(np.float32).astype(np.float64)
-        t = time.perf_counter()
-        ref1 = orc.irn_piccs(og1, b1, prior1, prior1, sp1["alpha"], sp1["lam"], sp1["tau"],
-                             sp1["n_outer"], sp1["n_inner"])
-        t_or1 = time.perf_counter() - t
-        g1 = cbct.Geometry.from_dict(gd1)
-        for name, pr in (("fp32", cbct.PREC_FP32), ("mixed_bf16", cbct.PREC_MIXED_BF16),
-                         ("mixed_f16", cbct.PREC_MIXED_F16)):
-            if name not in forms:
-                continue
-            x1 = torch.from_numpy(prior1.astype(np.float32)).to(dev)
-            cbct.solve(g1, torch.from_numpy(b1.astype(np.float32)).to(dev), x1.clone(), x1,
-                       cbct.SolveParams(sp1["alpha"], sp1["lam"], sp1["tau"], sp1["n_outer"],
-                                        sp1["n_inner"], precision=pr), report=False)
-            xg1 = x1.cpu().numpy().astype(np.float64)
-            forms[name]["rel_l2_vs_fp64_oracle_c1"] = float(
-                np.linalg.norm(xg1 - ref1.x) / np.linalg.norm(ref1.x))
-        cpu["oracle_c1_solve_s"] = round(t_or1, 2)
-
-    serving = None
-    if not args.no_serve:
-        serving = serving_bench(args, cbct, synth, np, torch, dev)
-
+    gd, sp = c5["gd"], c5["sp"]
     out = {
         "metric": "Gvoxel-proj/s for A and A^T; s/recon + p99 latency, FP32 vs mixed",
-        "value": round(value, 3),
+        "value": f32["value_gvoxel_proj_s"],
         "unit": "Gvoxel-proj/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(ms_per_step, 3),
+        "ms_per_step": round(1e3 * f32["s_per_recon"], 3),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
         "config": {
-            "workload": f"{wl}: {gd['nx']}x{gd['ny']}x{gd['nz']} volume, {V} views, "
-                        f"{gd['nu']}x{gd['nv']} detector, IRN-PICCS {p.n_outer}x{p.n_inner} "
-                        f"LSQR, fp32 storage, fp64 scalars",
-            "voxel_proj_per_step": vox_proj_step,
-            "products_per_step": products,
-            "s_per_recon": round(ms_per_step / 1e3, 4),
-            "step_ms_p50": round(float(np.percentile(step_ms, 50)), 3),
-            "step_ms_max": round(float(max(step_ms)), 3),
-            "A_ms": round(t_fwd, 4), "AT_ms": round(t_back, 4),
-            "A_gvoxel_proj_s": round(gvp_fwd, 2), "AT_gvoxel_proj_s": round(gvp_back, 2),
-            "nnz": nnz,
-            "rel_err_vs_truth": round(err_truth, 5),
-            "rel_err_prior_vs_truth": round(err_prior, 5),
-            "fdk_ms": round(fdk_ms, 3),
-            "rel_err_fdk_vs_truth": round(err_fdk, 5),
-            "prior": args.prior,
+            "workload": f"c5: ten-scan repeated sequence, {gd['nx']}x{gd['ny']}x{gd['nz']} volume "
+                        f"at {gd['vx']} mm, {gd['n_views']} views, {gd['nu']}x{gd['nv']} detector "
+                        f"at {gd['du']} mm, needle +3 mm per scan, IRN-PICCS "
+                        f"{sp['n_outer']}x{sp['n_inner']} LSQR per scan warm-started from the "
+                        f"previous reconstruction, fp32 storage, fp64 Krylov scalars",
+            "voxel_proj_per_step": c5["vox_proj_step"],
+            "products_per_step": c5["products"],
+            "s_per_recon": f32["s_per_recon"],
+            "step_ms_p50": f32["step_ms_p50"],
+            "step_ms_max": f32["step_ms_max"],
+            "rel_err_vs_truth": f32["rel_err_vs_truth"],
+            "rel_err_prior_vs_truth": f32["rel_err_prior_vs_truth"],
+            **c5["ops"],
         },
         "precision_forms": forms,
+        # every form against the FP64 oracle on reduced problems (labelled by case)
+        "precision_vs_fp64_oracle": errs,
+        "c2": c2,
         "serving": serving,
-        "roofline": roofline,
+        "roofline": c5["roofline"],
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -253,7 +253,11 @@ int piccs_workspace_bytes(const cbct_geom *g, const piccs_params *p, size_t *byt
  * entry (warm start) and x_K on return.  workspace: >= piccs_workspace_bytes,
  * device, 256-byte aligned.  If rep != NULL the call synchronises the stream
  * and fills the report; otherwise it returns after enqueueing.
- * Errors: CBCT_ERR_INVALID, CBCT_ERR_DEVICE.
+ * A norm that comes out non-finite (NaN or Inf in b, x_0 or x_p, or an
+ * overflow) stops the solve at that point, leaving the last finite iterate in
+ * x; with rep != NULL the call then returns CBCT_ERR_NUMERIC (the report is
+ * filled first).
+ * Errors: CBCT_ERR_INVALID, CBCT_ERR_DEVICE, CBCT_ERR_NUMERIC.
  */
 int piccs_krylov_solve(const cbct_geom *g, const float *b, const float *xp, float *x,
                        const piccs_params *p, void *workspace, size_t ws_bytes,
@@ -303,7 +307,8 @@ typedef struct {
 } cbct_request;
 
 typedef struct {
-    int32_t status;        /* CBCT_OK or the request's error                         */
+    int32_t status;        /* CBCT_OK or the request's error (CBCT_ERR_NUMERIC: a non-
+                              finite norm, e.g. NaN or Inf in b or the start image)  */
     double t_submit;       /* submit returned                                        */
     double t_admit;        /* admitted: its work was enqueued on the device          */
     double t_done;         /* result ready to poll                                   */

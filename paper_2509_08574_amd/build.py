@@ -57,6 +57,23 @@ def build_sim(verbose: bool = False) -> str:
     return SIM_LIB
 
 
+PROBE = os.path.join(HERE, "valu_probe")
+
+
+def build_probe(verbose: bool = False) -> str:
+    """The VALU issue-rate probe (a measurement helper of bench.py's roofline,
+    not part of the library)."""
+    tmp = PROBE + ".tmp"
+    cmd = [HIPCC, *FLAGS, "-x", "hip", os.path.join(CSRC, "valu_probe.hip"), "-o", tmp]
+    if verbose:
+        print(" ".join(cmd), file=sys.stderr)
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"hipcc failed for valu_probe.hip:\n{r.stdout}\n{r.stderr}")
+    os.replace(tmp, PROBE)
+    return PROBE
+
+
 def build(verbose: bool = False) -> str:
     outdir = os.path.join(HERE, "_build")
     os.makedirs(outdir, exist_ok=True)
@@ -69,6 +86,7 @@ def build(verbose: bool = False) -> str:
     subprocess.run(cmd, check=True)
     os.replace(tmp, LIB)
     build_sim(verbose)
+    build_probe(verbose)
     return LIB
 
 

@@ -142,6 +142,8 @@ void solve_enqueue(cbct_geom *g, const float *b, const float *xp, float *x,
                    double *sc_host, double *hist_host);
 int solve_scalar_count();
 void report_from_scalars(const double *sc, piccs_report *rep);
+// True if the solve whose scalar block this is stopped on a non-finite norm.
+bool solve_numeric_fault(const double *sc);
 
 // ---- projector launchers (proj.hip) ----
 // Forward epilogue modes.
@@ -157,6 +159,11 @@ struct FwdArgs {
     const int *brk;          // FWD_SOLVER: breakdown flag (2 = stopped)
     unsigned long long *count;  // FWD_COUNT
     float scale;             // FWD_PLAIN: output multiplier (value of one stored unit)
+    // FWD_SOLVER, mixed forms: 16-bit copy of the new u-hat for the adjoint
+    // (bf16, or fp16 holding u-hat * *u16_scale, a power of two), or null
+    void *u16;
+    int u16_dt;              // CBCT_BF16 or CBCT_F16
+    const double *u16_scale;
 };
 // Internal storage codes beyond cbct_dtype: the solver's 16-bit shadow of a
 // volume kept as one 32-bit word per cell holding (cell k, cell k + 1) in its
@@ -169,8 +176,12 @@ void launch_forward(const GeoK &G, int mode, const FwdArgs &a, hipStream_t s,
 int64_t forward_blocks(const GeoK &G);
 
 // Back projection of column projections y-hat (already multiplied by the ray
-// length L) into a padded column volume (pads written as zero).
-void launch_back(const GeoK &G, const float *yhat, float *out, const int *brk, hipStream_t s);
+// length L) into a padded column volume (pads written as zero).  With
+// dt = CBCT_BF16 / CBCT_F16, yhat holds 16-bit values (fp16: y-hat * *scale, a
+// power of two, divided out at the store) and must be readable 8 bytes past its
+// last sample.
+void launch_back(const GeoK &G, const void *yhat, float *out, const int *brk, hipStream_t s,
+                 int dt = CBCT_F32, const double *scale = nullptr);
 
 // Batched 2-D transpose: out[b*ob + c*oc + r + ooff] = in[b*ib + r*ir + c + ioff] (* L(c,r)
 // when Lu2/Lv2 are non-null: used for projections with u = c, v = r).
@@ -184,6 +195,7 @@ void vol_to_cols(const GeoK &G, const float *x, float *cols, hipStream_t s);
 void cols_to_vol(const GeoK &G, const float *cols, float *x, hipStream_t s);
 void proj_to_cols(const GeoK &G, const float *y, float *ycol, bool scale_by_L, hipStream_t s);
 void cols_to_proj(const GeoK &G, const float *ycol, float *y, hipStream_t s);
+
 
 // y = A x from an API-layout volume of storage type xt (value = stored * x_scale)
 // into API-layout projections y, through the column layouts held in caller

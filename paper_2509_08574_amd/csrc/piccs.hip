@@ -30,6 +30,8 @@ enum Sc {
     SC_M1, SC_P1, SC_ZERO,
     SC_INNER_DONE, SC_OUTER_DONE, SC_NBRK,
     SC_V16_SCALE,  // power-of-two scale of the 16-bit shadow of V (mixed forms)
+    SC_U16_SCALE,  // power-of-two scale of the 16-bit copy of u-hat (mixed fp16 form)
+    SC_NUMERIC,    // 1 once a norm came out non-finite (the solve stopped there)
     SC_COUNT = 32
 };
 // flag 0: breakdown state of the current inner solve: 0 running, 1 last
@@ -325,10 +327,19 @@ enum RedMode { RED_INIT_BETA = 0, RED_INIT_ALPHA, RED_BETA, RED_ALPHA };
 
 // One block of 1024 threads: sum two partial arrays in a fixed order (so the
 // result is bit-reproducible), then advance LSQR's scalar recurrence.
+// Power-of-two scale for the fp16 copy of u-hat written by the next inner
+// forward: u-hat = L u with |u| = beta_next, estimated by the current beta, so
+// its samples have root-mean-square about beta L_ref / sqrt(N); uref = sqrt(N) /
+// L_ref brings that to about 1.  1 for bf16 / fp32.
+__device__ __forceinline__ double uhat_scale(int dt, double beta, double uref) {
+    if (dt != CBCT_F16 || !(beta > 0.0)) return 1.0;
+    return exp2(rint(log2(uref / beta)));
+}
+
 template <int MODE>
 __global__ void __launch_bounds__(1024)
 k_red(const double *__restrict__ p0, int64_t n0, const double *__restrict__ p1, int64_t n1,
-      double *sc, int *fl, double *hist, int it, int dt, double nvox) {
+      double *sc, int *fl, double *hist, int it, int dt, double nvox, double uref) {
     const int brk = fl[0];
     if (brk == 2) return;
     if (MODE == RED_BETA && brk == 1) {
@@ -359,6 +370,11 @@ k_red(const double *__restrict__ p0, int64_t n0, const double *__restrict__ p1, 
     }
     if (threadIdx.x != 0) return;
     const double nrm = sqrt(red[0]);
+    if (!isfinite(nrm)) {  // NaN / Inf in b, x_0 or x_p, or an overflow: stop here
+        sc[SC_NUMERIC] = 1.0;
+        fl[0] = 2;
+        return;
+    }
     if (MODE == RED_INIT_BETA) {            // beta_1 u_1 = b~ - A~ x_0
         sc[SC_BETA] = nrm;
         if (!(nrm > kTiny)) { fl[0] = 2; return; }
@@ -378,6 +394,7 @@ k_red(const double *__restrict__ p0, int64_t n0, const double *__restrict__ p1, 
         sc[SC_FWD_S1] = 1.0 / (nrm * sv);  // the projector reads V * sv
         sc[SC_REG_S1] = 1.0 / nrm;
         sc[SC_FWD_S2] = sc[SC_REG_S2] = -nrm / beta;
+        sc[SC_U16_SCALE] = uhat_scale(dt, beta, uref);
     } else if (MODE == RED_BETA) {          // beta u = A~ v - alpha u
         const double alpha = sc[SC_ALPHA];
         sc[SC_BETA] = nrm;
@@ -408,6 +425,7 @@ k_red(const double *__restrict__ p0, int64_t n0, const double *__restrict__ p1, 
             sc[SC_FWD_S1] = 1.0 / (alpha * sv);  // the projector reads V * sv
             sc[SC_REG_S1] = 1.0 / alpha;
             sc[SC_FWD_S2] = sc[SC_REG_S2] = -alpha / beta;
+            sc[SC_U16_SCALE] = uhat_scale(dt, beta, uref);
         }
     }
 }
@@ -418,6 +436,7 @@ __global__ void k_solve_begin(double *sc, int *fl, double *hist, int nh) {
     sc[SC_M1] = -1.0;
     sc[SC_P1] = 1.0;
     sc[SC_V16_SCALE] = 1.0;
+    sc[SC_U16_SCALE] = 1.0;
     fl[0] = 0;
 }
 
@@ -441,6 +460,7 @@ struct Workspace {
     size_t v16_bytes;
     int64_t cstride;                                // floats between components
     float *bhat, *uhat;
+    unsigned short *uhat16;  // 16-bit copy of u-hat read by the adjoint (mixed forms)
     double *pf, *pr, *pa;  // partials: forward, regF, regA
     int64_t nf, nr;
     float *Q;              // reorthogonalisation basis: n_inner padded volumes (base P)
@@ -477,6 +497,8 @@ static Workspace carve(const cbct_geom *g, const GeoK &G, const piccs_params *p,
     }
     W.bhat = (float *)take(pb);
     W.uhat = (float *)take(pb);
+    if (p->precision != CBCT_PREC_FP32)  // 2 bytes per sample, read up to 8 bytes past the last
+        W.uhat16 = (unsigned short *)take(sizeof(unsigned short) * (size_t)g->n_proj() + 8);
     W.pf = (double *)take(sizeof(double) * (size_t)W.nf);
     W.pr = (double *)take(sizeof(double) * (size_t)W.nr);
     W.pa = (double *)take(sizeof(double) * (size_t)W.nr);
@@ -535,6 +557,7 @@ void solve_enqueue(cbct_geom *g, const float *b, const float *xp, float *x,
                                                           : CBCT_F32;
     if (dt != CBCT_F32) launch_fill((float *)W.V16buf, (int64_t)(W.v16_bytes / 4), 0.0f, s);
     const double nvox = (double)g->n_vox();
+    const double uref = std::sqrt((double)g->n_proj()) / g->d.dsd;
     // q: where the normalised v goes for reorthogonalisation, or null
     auto xw = [&](float *q) {
         if (dt == CBCT_BF16)
@@ -576,14 +599,15 @@ void solve_enqueue(cbct_geom *g, const float *b, const float *xp, float *x,
         hipLaunchKernelGGL(k_outer_begin, dim3(1), dim3(1), 0, s, W.sc, W.fl);
         hipLaunchKernelGGL(k_weights, dim3(nvb), dim3(256), 0, s, G, W.x, W.xp, tau2, W.W1,
                            W.W2);
-        // beta_1 u_1 = b~ - A~ x_{k-1}
+        // beta_1 u_1 = b~ - A~ x_{k-1} (float32 throughout, as the restart's adjoint)
         fa.vol = W.x; fa.uin = W.bhat; fa.s1 = W.sc + SC_M1; fa.s2 = W.sc + SC_P1;
+        fa.u16 = nullptr;
         launch_forward(G, FWD_SOLVER, fa, s);
         hipLaunchKernelGGL(regF_init, dim3(nvb), dim3(256), 0, s, G, W.x, W.xp, W.W1,
                            W.W2, W.u1, W.u2, W.cstride, alpha, lam, W.sc + SC_M1,
                            W.sc + SC_ZERO, W.pr, W.fl);
         hipLaunchKernelGGL(k_red<RED_INIT_BETA>, dim3(1), dim3(1024), 0, s, W.pf, W.nf,
-                           W.pr, W.nr, W.sc, W.fl, W.hist, 0, dt, nvox);
+                           W.pr, W.nr, W.sc, W.fl, W.hist, 0, dt, nvox, uref);
         // alpha_1 v_1 = A~^T u_1
         launch_back(G, W.uhat, W.t, W.fl, s);
         hipLaunchKernelGGL(regA, dim3(nvb), dim3(256), 0, s, G, W.t, W.W1, W.W2, W.u1,
@@ -591,11 +615,13 @@ void solve_enqueue(cbct_geom *g, const float *b, const float *xp, float *x,
                            W.sc + SC_BACK_S2, W.pa, W.fl);
         hipLaunchKernelGGL(k_red<RED_INIT_ALPHA>, dim3(1), dim3(1024), 0, s, W.pa, W.nr,
                            (const double *)nullptr, (int64_t)0, W.sc, W.fl, W.hist, 0, dt,
-                           nvox);
+                           nvox, uref);
         xw(basis(0));
         for (int ki = 0; ki < p->n_inner; ++ki, ++it_global) {
             fa.vol = dt == CBCT_F32 ? (const void *)W.V : (const void *)W.V16;
             fa.uin = W.uhat; fa.s1 = W.sc + SC_FWD_S1; fa.s2 = W.sc + SC_FWD_S2;
+            // mixed forms: the inner forward also writes the adjoint's 16-bit input
+            fa.u16 = W.uhat16; fa.u16_dt = dt; fa.u16_scale = W.sc + SC_U16_SCALE;
             launch_forward(G, FWD_SOLVER, fa, s,
                            dt == CBCT_BF16  ? CBCT_BF16_PAIR
                            : dt == CBCT_F16 ? CBCT_F16_PAIR
@@ -604,8 +630,11 @@ void solve_enqueue(cbct_geom *g, const float *b, const float *xp, float *x,
                                (const float *)nullptr, W.W1, W.W2, W.u1, W.u2, W.cstride,
                                alpha, lam, W.sc + SC_REG_S1, W.sc + SC_REG_S2, W.pr, W.fl);
             hipLaunchKernelGGL(k_red<RED_BETA>, dim3(1), dim3(1024), 0, s, W.pf, W.nf,
-                               W.pr, W.nr, W.sc, W.fl, W.hist, it_global, dt, nvox);
-            launch_back(G, W.uhat, W.t, W.fl, s);
+                               W.pr, W.nr, W.sc, W.fl, W.hist, it_global, dt, nvox, uref);
+            if (dt == CBCT_F32)
+                launch_back(G, W.uhat, W.t, W.fl, s);
+            else
+                launch_back(G, W.uhat16, W.t, W.fl, s, dt, W.sc + SC_U16_SCALE);
             hipLaunchKernelGGL(regA, dim3(nvb), dim3(256), 0, s, G, W.t, W.W1, W.W2, W.u1,
                                W.u2, W.cstride, alpha, lam, W.V, W.sc + SC_BACK_S1,
                                W.sc + SC_BACK_S2, W.pa, W.fl);
@@ -613,7 +642,7 @@ void solve_enqueue(cbct_geom *g, const float *b, const float *xp, float *x,
             hipLaunchKernelGGL(k_red<RED_ALPHA>, dim3(1), dim3(1024), 0, s,
                                reorth ? W.pq : W.pa, reorth ? (int64_t)kQBlocks : W.nr,
                                (const double *)nullptr, (int64_t)0, W.sc, W.fl, W.hist,
-                               it_global, dt, nvox);
+                               it_global, dt, nvox, uref);
             xw(basis(ki + 1));
         }
     }
@@ -630,6 +659,8 @@ void solve_enqueue(cbct_geom *g, const float *b, const float *xp, float *x,
 }
 
 int solve_scalar_count() { return SC_COUNT; }
+
+bool solve_numeric_fault(const double *sc) { return sc[SC_NUMERIC] != 0.0; }
 
 void report_from_scalars(const double *sc, piccs_report *rep) {
     rep->inner_done = (int32_t)sc[SC_INNER_DONE];
@@ -723,6 +754,10 @@ int piccs_krylov_solve(const cbct_geom *gc, const float *b, const float *xp, flo
             report_from_scalars(sc.data(), rep);
             if (rep->resid_hist)
                 for (int q = 0; q < nh; ++q) rep->resid_hist[q] = hist[(size_t)q];
+            if (solve_numeric_fault(sc.data()))
+                throw Error(CBCT_ERR_NUMERIC,
+                            "non-finite norm in the solve (NaN or Inf in b, x0 or xp, or an "
+                            "overflow); x holds the last finite iterate");
         }
         return CBCT_OK;
     } catch (const std::exception &e) {

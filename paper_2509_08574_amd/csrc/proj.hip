@@ -17,6 +17,7 @@
 // lane then gathers, for each of its cells, a short window of detector rows
 // whose chords with that cell are the forward kernel's c0 / c1 bit for bit.
 // Every cell is summed in a fixed order and written once; no atomics.
+#include <hip/hip_bf16.h>
 #include <hip/hip_fp16.h>
 
 #include <algorithm>
@@ -387,6 +388,15 @@ k_fwd(GeoK G, FwdArgs a) {
             if (ok) {
                 a.out[o] = un;
                 sq += (double)un * (double)un / (double)L2;  // |u|^2 = u-hat^2 / L^2
+                // the adjoint's 16-bit input (mixed forms): the same value rounded
+                if (a.u16) {
+                    unsigned short h;
+                    if (a.u16_dt == CBCT_BF16)
+                        h = __bfloat16_as_ushort(__float2bfloat16(un));
+                    else
+                        h = __half_as_ushort(__float2half(un * (float)*a.u16_scale));
+                    ((unsigned short *)a.u16)[o] = h;
+                }
             }
         }
     }
@@ -472,11 +482,56 @@ void launch_forward(const GeoK &G, int mode, const FwdArgs &a, hipStream_t s, in
 #endif
 constexpr int kBackTileW = CBCT_BACK_TILE_W, kBackTileH = CBCT_BACK_TILE_H;
 
-template <int C>
+// Window samples of A^T's input: float32, or 16-bit values widened on load.
+// A 16-bit window of up to four rows is one 8-byte read at the window's first
+// row (2-byte aligned; the device runs in unaligned-access mode), whose last
+// sample may lie past the detector column (the buffer is padded by 8 bytes).
+template <int DT>
+struct BackIn;
+template <>
+struct BackIn<CBCT_F32> {
+    using T = float;
+    template <int C>
+    __device__ static void window(const float *y, float (&v)[C]) {
+#pragma unroll
+        for (int c = 0; c < C; ++c) v[c] = y[c];
+    }
+};
+template <int DT>
+struct BackIn16 {
+    using T = unsigned short;
+    __device__ static float widen(unsigned short h) {
+        if constexpr (DT == CBCT_BF16)
+            return __uint_as_float((unsigned)h << 16);
+        else
+            return __half2float(__ushort_as_half(h));
+    }
+    template <int C>
+    __device__ static void window(const unsigned short *y, float (&v)[C]) {
+        if constexpr (C <= 4) {
+            const uint2 w = *(const uint2 *)y;
+            const unsigned h[4] = {w.x & 0xffffu, w.x >> 16, w.y & 0xffffu, w.y >> 16};
+#pragma unroll
+            for (int c = 0; c < C; ++c) v[c] = widen((unsigned short)h[c]);
+        } else {
+#pragma unroll
+            for (int c = 0; c < C; ++c) v[c] = widen(y[c]);
+        }
+    }
+};
+template <>
+struct BackIn<CBCT_BF16> : BackIn16<CBCT_BF16> {};
+template <>
+struct BackIn<CBCT_F16> : BackIn16<CBCT_F16> {};
+
+template <int C, int DT>
 __global__ void __launch_bounds__(256)
-k_back(GeoK G, const float *__restrict__ yhat, float *__restrict__ out, const int *brk,
-       float a_ref, float z_lo_mm, float fv_off, float fu_margin, int kspan, int nq) {
+k_back(GeoK G, const void *__restrict__ yin, float *__restrict__ out, const int *brk,
+       const double *in_scale, float a_ref, float z_lo_mm, float fv_off, float fu_margin,
+       int kspan, int nq) {
     if (brk && *brk == 2) return;
+    using YT = typename BackIn<DT>::T;
+    const YT *yhat = (const YT *)yin;
     extern __shared__ float lds[];
     float2 *zrs = (float2 *)lds;  // per-row (rg, cz)
     for (int t = threadIdx.x; t < G.nv; t += 256) {
@@ -571,7 +626,7 @@ k_back(GeoK G, const float *__restrict__ yhat, float *__restrict__ out, const in
             // heights reached by row v over the interval: z = A v, A in [A1, A2]
             const float iA1 = __builtin_amdgcn_rcpf(fmaf(aa, G.dv, a_ref_dv));
             const float iA2 = __builtin_amdgcn_rcpf(fmaf(ab, G.dv, a_ref_dv));
-            const float *yrow = yhat + ((size_t)view * G.nu + iu) * G.nv;
+            const YT *yrow = yhat + ((size_t)view * G.nu + iu) * G.nv;
 #pragma unroll
             for (int q = 0; q < QM; ++q) {
                 if (q >= nq) break;
@@ -585,7 +640,10 @@ k_back(GeoK G, const float *__restrict__ yhat, float *__restrict__ out, const in
                 const float nflo = fmaf(-zk0[q], zk0[q] >= 0.0f ? iA2 : iA1, -fv_off);
                 const int m = (int)floorf(__builtin_amdgcn_fmed3f(nflo, nrwin, 0.0f));
                 const float2 *zq = (const float2 *)((const char *)zrs + __mul24(m, -8));
-                const float *yq = (const float *)((const char *)yrow + (uint32_t)__mul24(m, -4));
+                const YT *yq = (const YT *)((const char *)yrow +
+                                            (uint32_t)__mul24(m, -(int)sizeof(YT)));
+                float yv[C];
+                BackIn<DT>::template window<C>(yq, yv);
                 float a = acc[q];
 #pragma unroll
                 for (int c = 0; c < C; ++c) {
@@ -598,16 +656,18 @@ k_back(GeoK G, const float *__restrict__ yhat, float *__restrict__ out, const in
                     // clamp is non-decreasing in t and aa < ab, so hi - lo >= 0.
                     const float lo = __builtin_amdgcn_fmed3f(aa, zA, zB);
                     const float hi = __builtin_amdgcn_fmed3f(ab, zA, zB);
-                    a = fmaf(hi - lo, yq[c], a);
+                    a = fmaf(hi - lo, yv[c], a);
                 }
                 acc[q] = a;  // lanes past the column's end are never stored
             }
         }
     }
     float *oc = out + (size_t)col * G.Z;
+    // a scaled 16-bit input carries the power-of-two scale: divide it out (exact)
+    const float inv = DT == CBCT_F16 ? (float)(1.0 / *in_scale) : 1.0f;
 #pragma unroll
     for (int q = 0; q < QM; ++q)
-        if (kok[q]) oc[kbase + lane + 64 * q + 1] = acc[q];
+        if (kok[q]) oc[kbase + lane + 64 * q + 1] = DT == CBCT_F16 ? acc[q] * inv : acc[q];
     if (zs == 0 && lane == 0) oc[0] = 0.0f;
     if (zs == nzs - 1 && lane == 0) oc[G.nz + 1] = 0.0f;
 }
@@ -642,7 +702,9 @@ static int back_candidates(const GeoK &G) {
     return (int)std::floor(span * 1.02 + 0.01) + 1;
 }
 
-void launch_back(const GeoK &G, const float *yhat, float *out, const int *brk, hipStream_t s) {
+template <int DT>
+static void launch_back_dt(const GeoK &G, const void *yhat, float *out, const int *brk,
+                           const double *scale, hipStream_t s) {
     // cells per wave: 64 * nq, nq <= 8; columns taller than 512 cells are split
     const int nq = std::min(8, (G.nz + 63) / 64);
     const int kspan = 64 * nq;
@@ -660,23 +722,33 @@ void launch_back(const GeoK &G, const float *yhat, float *out, const int *brk, h
     // window of C rows; never more rows than the detector has
     const int C = std::min(back_candidates(G), G.nv);
     auto go = [&](auto kern) {
-        hipLaunchKernelGGL(kern, dim3((unsigned)nb), dim3(256), shm, s, G, yhat, out, brk, a_ref,
-                           z_lo_mm, fv_off, fu_margin, kspan, nq);
+        hipLaunchKernelGGL(kern, dim3((unsigned)nb), dim3(256), shm, s, G, yhat, out, brk, scale,
+                           a_ref, z_lo_mm, fv_off, fu_margin, kspan, nq);
     };
     switch (C) {
-        case 1: go(k_back<1>); break;
-        case 2: go(k_back<2>); break;
-        case 3: go(k_back<3>); break;
-        case 4: go(k_back<4>); break;
-        case 5: go(k_back<5>); break;
-        case 6: go(k_back<6>); break;
-        case 7: go(k_back<7>); break;
-        case 8: go(k_back<8>); break;
+        case 1: go(k_back<1, DT>); break;
+        case 2: go(k_back<2, DT>); break;
+        case 3: go(k_back<3, DT>); break;
+        case 4: go(k_back<4, DT>); break;
+        case 5: go(k_back<5, DT>); break;
+        case 6: go(k_back<6, DT>); break;
+        case 7: go(k_back<7, DT>); break;
+        case 8: go(k_back<8, DT>); break;
         default:
             throw Error(CBCT_ERR_INVALID, "detector rows too fine for the back projector (more "
                                           "than 8 rows can meet one voxel)");
     }
     CBCT_HIP(hipGetLastError());
+}
+
+void launch_back(const GeoK &G, const void *yhat, float *out, const int *brk, hipStream_t s,
+                 int dt, const double *scale) {
+    if (dt == CBCT_BF16)
+        launch_back_dt<CBCT_BF16>(G, yhat, out, brk, scale, s);
+    else if (dt == CBCT_F16)
+        launch_back_dt<CBCT_F16>(G, yhat, out, brk, scale, s);
+    else
+        launch_back_dt<CBCT_F32>(G, yhat, out, brk, scale, s);
 }
 
 // ---------------------------------------------------------------- layout kernels

@@ -238,6 +238,11 @@ struct cbct_server {
             if (j.status == CBCT_PENDING) {
                 report_from_scalars((const double *)P.r.p, &P.report);
                 j.status = CBCT_OK;
+                if (solve_numeric_fault((const double *)P.r.p)) {
+                    j.status = CBCT_ERR_NUMERIC;
+                    j.error = "non-finite norm in the solve (NaN or Inf in b or the start "
+                              "image, or an overflow)";
+                }
             }
             if (P.ev) S->free_events.push_back(P.ev);
             P.ev = nullptr;

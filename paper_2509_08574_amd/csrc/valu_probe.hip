@@ -1,0 +1,121 @@
+// VALU issue-rate probe for gfx950 (measurement helper of bench.py's roofline;
+// not part of the library).
+//
+// One kernel per instruction kind, each a long loop of 8 independent chains of
+// that one instruction (written in inline assembly so that the compiler can
+// neither fold nor reorder them), launched with 8 waves per SIMD on every CU.
+// Printed per kind: wave-instructions per second and the issue cycles one
+// wave64 instruction takes on its SIMD at the measured clock, which
+// classifies each kind as a 2-cycle (dual-issued), 4-cycle or 8-cycle
+// instruction.  Run it under rocprofv3 --pmc SQ_INSTS_VALU SQ_ACTIVE_INST_VALU2
+// to see which kinds the second VALU pipe takes.
+#include <hip/hip_runtime.h>
+
+#include <cstdio>
+
+#define CHECK(x)                                                                   \
+    do {                                                                           \
+        hipError_t e_ = (x);                                                       \
+        if (e_ != hipSuccess) {                                                    \
+            std::printf("HIP error %s at line %d\n", hipGetErrorString(e_), __LINE__); \
+            return 1;                                                              \
+        }                                                                          \
+    } while (0)
+
+constexpr int kChains = 8, kUnroll = 16;
+
+template <int KIND>
+__global__ void __launch_bounds__(256) probe(float *out, int iters, float a, float b) {
+    float f[kChains];
+    unsigned u[kChains];
+    const unsigned long long mask = 0x5555555555555555ull;
+#pragma unroll
+    for (int q = 0; q < kChains; ++q) {
+        f[q] = threadIdx.x * 1e-3f + q;
+        u[q] = threadIdx.x + q;
+    }
+    for (int it = 0; it < iters; ++it) {
+#pragma unroll
+        for (int r = 0; r < kUnroll; ++r) {
+#pragma unroll
+            for (int q = 0; q < kChains; ++q) {
+                if constexpr (KIND == 0) asm volatile("v_fma_f32 %0, %0, %1, %2" : "+v"(f[q]) : "v"(a), "v"(b));
+                if constexpr (KIND == 1) asm volatile("v_add_f32 %0, %0, %1" : "+v"(f[q]) : "v"(b));
+                if constexpr (KIND == 2) asm volatile("v_mul_f32 %0, %0, %1" : "+v"(f[q]) : "v"(a));
+                if constexpr (KIND == 3) asm volatile("v_add_u32 %0, %0, %1" : "+v"(u[q]) : "v"(it));
+                if constexpr (KIND == 4) asm volatile("v_and_b32 %0, %0, %1" : "+v"(u[q]) : "v"(it));
+                if constexpr (KIND == 5) asm volatile("v_min_f32 %0, %0, %1" : "+v"(f[q]) : "v"(b));
+                if constexpr (KIND == 6) asm volatile("v_med3_f32 %0, %0, %1, %2" : "+v"(f[q]) : "v"(a), "v"(b));
+                if constexpr (KIND == 7) asm volatile("v_cvt_flr_i32_f32 %0, %1" : "=v"(u[q]) : "v"(f[q]));
+                if constexpr (KIND == 8) asm volatile("v_mul_i32_i24 %0, %0, %1" : "+v"(u[q]) : "v"(it));
+                if constexpr (KIND == 9) asm volatile("v_cndmask_b32_e64 %0, %0, %1, %2" : "+v"(f[q]) : "v"(a), "s"(mask));
+                if constexpr (KIND == 10) asm volatile("v_fma_mix_f32 %0, %1, %2, %0 op_sel_hi:[0,1,0]" : "+v"(f[q]) : "v"(a), "v"(u[q]));
+                if constexpr (KIND == 11) asm volatile("v_rcp_f32 %0, %0" : "+v"(f[q]));
+            }
+        }
+    }
+    float s = 0.f;
+#pragma unroll
+    for (int q = 0; q < kChains; ++q) s += f[q] + (float)u[q];
+    if (s == 12345.678f) out[blockIdx.x] = s;  // keeps the chains live; never true in practice
+}
+
+static const char *kNames[] = {"v_fma_f32", "v_add_f32", "v_mul_f32", "v_add_u32",
+                               "v_and_b32", "v_min_f32", "v_med3_f32", "v_cvt_flr_i32_f32",
+                               "v_mul_i32_i24", "v_cndmask_b32_e64", "v_fma_mix_f32",
+                               "v_rcp_f32"};
+
+template <int KIND>
+int run(float *out, int blocks, int iters, int clock_khz) {
+    hipEvent_t e0, e1;
+    CHECK(hipEventCreate(&e0));
+    CHECK(hipEventCreate(&e1));
+    hipLaunchKernelGGL(probe<KIND>, dim3(blocks), dim3(256), 0, 0, out, iters, 0.999f, 0.001f);
+    CHECK(hipGetLastError());
+    CHECK(hipDeviceSynchronize());
+    const int reps = 3;
+    CHECK(hipEventRecord(e0, 0));
+    for (int r = 0; r < reps; ++r)
+        hipLaunchKernelGGL(probe<KIND>, dim3(blocks), dim3(256), 0, 0, out, iters, 0.999f, 0.001f);
+    CHECK(hipEventRecord(e1, 0));
+    CHECK(hipEventSynchronize(e1));
+    float ms = 0.f;
+    CHECK(hipEventElapsedTime(&ms, e0, e1));
+    ms /= reps;
+    const double instr = blocks * 4.0 * iters * kUnroll * kChains;  // chain instructions
+    const double rate = instr / (ms * 1e-3);
+    // issue cycles per wave64 instruction per SIMD at the nominal 2.4 GHz (256 CUs x 4 SIMDs)
+    const double cycles = 256.0 * 4.0 * 2.4e9 / rate;
+    std::printf("%-20s %9.3f ms  %8.1f G wave-instr/s  %5.2f issue cycles (2.4 GHz)\n",
+                kNames[KIND], ms, rate / 1e9, cycles);
+    (void)clock_khz;
+    CHECK(hipEventDestroy(e0));
+    CHECK(hipEventDestroy(e1));
+    return 0;
+}
+
+int main() {
+    const int blocks = 8192;  // 32 waves per CU: 8 per SIMD on 256 CUs
+    const int iters = 4000;
+    float *out = nullptr;
+    CHECK(hipMalloc(&out, sizeof(float) * blocks));
+    int clk = 0;
+    CHECK(hipDeviceGetAttribute(&clk, hipDeviceAttributeClockRate, 0));
+    std::printf("VALU issue-rate probe: %d blocks x 256 threads, %d x %d x %d instructions per "
+                "thread and kind\n", blocks, iters, kUnroll, kChains);
+    int rc = 0;
+    rc |= run<0>(out, blocks, iters, clk);
+    rc |= run<1>(out, blocks, iters, clk);
+    rc |= run<2>(out, blocks, iters, clk);
+    rc |= run<3>(out, blocks, iters, clk);
+    rc |= run<4>(out, blocks, iters, clk);
+    rc |= run<5>(out, blocks, iters, clk);
+    rc |= run<6>(out, blocks, iters, clk);
+    rc |= run<7>(out, blocks, iters, clk);
+    rc |= run<8>(out, blocks, iters, clk);
+    rc |= run<9>(out, blocks, iters, clk);
+    rc |= run<10>(out, blocks, iters, clk);
+    rc |= run<11>(out, blocks, iters, clk);
+    CHECK(hipFree(out));
+    return rc;
+}

@@ -223,8 +223,10 @@ def test_queue_limit(orc, lib):
     p = lib.SolveParams(1.0, 1.0, 0.1, 3, 20)
     with lib.Server(hbm_budget_bytes=1 << 30, max_slots=1, max_queue=2) as srv:
         srv.add_prior(6, g, xp)
-        # one slot, two waiting: the limit is hit after two accepted requests
-        # (none admitted yet) or three (the first already on the device)
+        # one slot, two waiting: submitting 50 in a row is refused with BUSY at
+        # some point (how many are accepted first depends on how fast the device
+        # takes the first; the exact count is checked in the scheduler's CPU
+        # simulation), and every accepted request completes with the same result
         got, busy = [], False
         for _ in range(50):
             try:
@@ -233,7 +235,26 @@ def test_queue_limit(orc, lib):
                 assert e.code == lib.ERR_BUSY
                 busy = True
                 break
-        assert busy and 2 <= len(got) <= 3
+        assert busy and len(got) >= 2
         outs = [srv.wait(t, np.empty(xp.shape, np.float32))[1] for t in got]
     for x in outs[1:]:
         assert np.array_equal(x, outs[0])            # same request, same result
+
+
+def test_non_finite_scan_fails_with_numeric_error(orc, lib):
+    """A NaN in a request's projections stops its solve and the request fails
+    with CBCT_ERR_NUMERIC; the next request of the patient is unaffected."""
+    g = geom(32, 12)
+    xp = patient(orc, 7, 32)
+    b = request_b(orc, g, xp, 2.0, 71)
+    bad = b.copy()
+    bad.reshape(-1)[1234] = np.nan
+    p = lib.SolveParams(1.0, 1.0, 0.1, 1, 3)
+    with lib.Server(hbm_budget_bytes=1 << 30, max_slots=2) as srv:
+        srv.add_prior(7, g, xp)
+        rc, _, info = srv.wait(srv.submit(7, g, bad, p, lib.X0_PRIOR),
+                               np.empty(xp.shape, np.float32))
+        assert rc == lib.ERR_NUMERIC and info["status"] == lib.ERR_NUMERIC
+        assert "non-finite" in info["error"]
+        rc, x, _ = srv.wait(srv.submit(7, g, b, p, lib.X0_PRIOR), np.empty(xp.shape, np.float32))
+        assert rc == lib.OK and np.isfinite(x).all()

@@ -111,6 +111,35 @@ def test_prior_fixed_point(orc, lib):
     assert rel(xg, prior) <= 1e-5
 
 
+def test_non_finite_input_returns_numeric_error(orc, lib):
+    """NaN in b, or Inf in x_0: the solve stops at the first non-finite norm and
+    returns CBCT_ERR_NUMERIC (with a report); x keeps its last finite iterate."""
+    import torch
+    d, og, prior, cur, b, sp = c1_inputs(orc)
+    gg = lib.Geometry.from_dict(d)
+    p = lib.SolveParams(sp["alpha"], sp["lam"], sp["tau"], 1, 3)
+    bad = b.copy()
+    bad.reshape(-1)[777] = np.nan
+    x = dev(prior)
+    with pytest.raises(lib.CbctError) as ei:
+        lib.solve(gg, dev(bad), dev(prior), x, p)
+    assert ei.value.code == lib.ERR_NUMERIC
+    assert torch.isfinite(x).all()
+    assert np.array_equal(host(x), prior)   # stopped before the first update
+    x0 = prior.copy()
+    x0.reshape(-1)[4321] = np.inf
+    x = dev(x0)
+    with pytest.raises(lib.CbctError) as ei:
+        lib.solve(gg, dev(b), dev(prior), x, p)
+    assert ei.value.code == lib.ERR_NUMERIC
+    # the same call without a report only enqueues; a finite solve after it is clean
+    x = dev(prior)
+    lib.solve(gg, dev(bad), dev(prior), x, p, report=False)
+    x = dev(prior)
+    _, rep = lib.solve(gg, dev(b), dev(prior), x, p)
+    assert rep["inner_done"] == 3 and rep["breakdown"] == 0
+
+
 def test_solve_is_deterministic(orc, lib):
     d, og, prior, cur, b, sp = c1_inputs(orc)
     p = lib.SolveParams(sp["alpha"], sp["lam"], sp["tau"], 2, 3)
