@@ -37,6 +37,9 @@ HBM_PEAK_GBS = 8000.0
 # 24-bit multiplies, VOP3 selects and shifts) or 8 cycles (reciprocal), as the
 # issue-rate probe measures on the device.
 SIMD_ISSUE_PEAK_CYCLES_S = 256 * 4 * 2.4e9
+# Vector-memory data path: one texture-data (TD) unit per CU, busy at most every
+# cycle; a probe of plain loads from L2 keeps it busy about all of the time.
+TD_PEAK_BUSY_CYCLES_S = 256 * 2.4e9
 
 
 def log(*a):
@@ -122,37 +125,46 @@ def projector_pair(args, cbct, torch, g, xc, ywc, stream, workload):
 def roofline(dom, nnz, workload):
     """Roofline of the dominant projector kernel.
 
-    Both projectors are gathers whose operands come mostly from L2 and L1, so
-    their HBM traffic is far below what they consume (`effective_GBps` is the
-    operand-bytes rate, 4 B per chord, which exceeds the HBM peak).  What binds
-    them is instruction issue: the VALU issue cycles the kernel's instructions
-    occupy, over the chip's issue capacity.  `achieved` is that per-launch
-    demand (recorded from the committed profile of the same sources) over this
-    run's event-timed launch."""
+    Both projectors are gathers whose operands come mostly from L2 and L1: their
+    HBM traffic stays well below the HBM peak, and the operand-bytes rate (4 B
+    per chord, `effective_GBps`) exceeds it.  Two on-chip resources bound them:
+    VALU issue (`alu`: the issue cycles the kernel's instructions occupy on the
+    main VALU pipe, over 1024 SIMDs x 2.4 GHz) and the vector-memory data path
+    (`vmem`: busy cycles of the 256 texture-data units, over 256 x 2.4 GHz).
+    Both per-launch figures come from the committed profile of the same
+    sources and are divided by this run's event-timed launch; the one closer to
+    its peak is reported as the bound."""
     kernel, t_ms, opbytes = dom
+    t = t_ms * 1e-3
     cyc = recorded_profile(kernel, workload, "valu_issue_cycles_per_launch")
+    td = recorded_profile(kernel, workload, "td_busy_cycles_per_launch")
     traffic = recorded_profile(kernel, workload, "traffic_bytes_per_launch")
-    r = {"bound": "alu", "kernel": kernel, "achieved": None,
-         "peak": round(SIMD_ISSUE_PEAK_CYCLES_S / 1e9, 1),
-         "unit": "G VALU issue cycles/s (SIMD-cycles)", "frac": None, "traffic": traffic,
-         "avg_launch_ms": round(t_ms, 4), "units_per_launch": nnz, "unit_name": "chord",
-         "valu_issue_cycles_per_launch": cyc,
-         "effective_GBps": round(opbytes / (t_ms * 1e-3) / 1e9, 1),
-         "profile": f"profiles/{kernel}_{workload}.md"}
+    parts = {}
     if cyc:
-        ach = cyc / (t_ms * 1e-3)
-        r["achieved"] = round(ach / 1e9, 1)
-        r["frac"] = round(ach / SIMD_ISSUE_PEAK_CYCLES_S, 4)
+        parts["alu"] = {"achieved": round(cyc / t / 1e9, 1),
+                        "peak": round(SIMD_ISSUE_PEAK_CYCLES_S / 1e9, 1),
+                        "unit": "G VALU issue cycles/s (main pipe, SIMD-cycles)",
+                        "frac": round(cyc / t / SIMD_ISSUE_PEAK_CYCLES_S, 4)}
+    if td:
+        parts["vmem"] = {"achieved": round(td / t / 1e9, 1),
+                         "peak": round(TD_PEAK_BUSY_CYCLES_S / 1e9, 1),
+                         "unit": "G texture-data busy cycles/s (256 units)",
+                         "frac": round(td / t / TD_PEAK_BUSY_CYCLES_S, 4)}
     if traffic:
-        r["hbm"] = {"achieved_GBps": round(traffic / (t_ms * 1e-3) / 1e9, 1),
-                    "peak_GBps": HBM_PEAK_GBS,
-                    "frac": round(traffic / (t_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
-    for key, name in (("td_busy_fraction", "texture_data_busy"),
-                      ("ta_busy_fraction", "texture_address_busy"),
-                      ("l2_hit_rate", "l2_hit_rate")):
-        v = recorded_profile(kernel, workload, key)
-        if v is not None:
-            r.setdefault("measured", {})[name] = v
+        parts["hbm"] = {"achieved": round(traffic / t / 1e9, 1), "peak": HBM_PEAK_GBS,
+                        "unit": "GB/s (measured FETCH_SIZE + WRITE_SIZE)",
+                        "frac": round(traffic / t / 1e9 / HBM_PEAK_GBS, 4)}
+    bound = max(("alu", "vmem"), key=lambda k: parts[k]["frac"] if k in parts else -1.0)
+    main = parts.get(bound, {})
+    r = {"bound": bound if main else None, "kernel": kernel, "achieved": main.get("achieved"),
+         "peak": main.get("peak"), "unit": main.get("unit"), "frac": main.get("frac"),
+         "traffic": traffic, "avg_launch_ms": round(t_ms, 4), "units_per_launch": nnz,
+         "unit_name": "chord", "effective_GBps": round(opbytes / t / 1e9, 1),
+         "profile": f"profiles/{kernel}_{workload}.md"}
+    r.update(parts)
+    l2 = recorded_profile(kernel, workload, "l2_hit_rate")
+    if l2 is not None:
+        r["l2_hit_rate"] = l2
     return r
 
 
@@ -225,15 +237,23 @@ def repeated_scans(args, cbct, synth, np, torch, dev, stream):
         tr = truth(last)
         err = float(torch.linalg.norm(x - tr) / torch.linalg.norm(tr))
         err_prior = float(torch.linalg.norm(xp - tr) / torch.linalg.norm(tr))
+        # the change against the prior is the needle: its recovery (1 = none of it,
+        # 0 = exact) over the needle's voxels
+        nd = needles[last]
+        chg = float(torch.linalg.norm(x.view(-1)[nd] - tr.view(-1)[nd])
+                    / torch.linalg.norm(tr.view(-1)[nd] - xp.view(-1)[nd]))
         forms[name] = {"s_per_recon": round(total / args.steps, 4),
                        "step_ms_p50": round(float(np.percentile(step_ms, 50)), 2),
                        "step_ms_max": round(float(max(step_ms)), 2),
                        "value_gvoxel_proj_s": round(vox_proj_step * args.steps / total / 1e9, 3),
                        "last_scan": last + 1, "rel_err_vs_truth": round(err, 5),
-                       "rel_err_prior_vs_truth": round(err_prior, 5)}
+                       "rel_err_prior_vs_truth": round(err_prior, 5),
+                       "improves_on_prior": err < err_prior,
+                       "needle_change_err": round(chg, 4)}
         xs[name] = x
         log(f"[bench] 512x512x400 {name}: {args.steps} steps, {1e3 * total / args.steps:.1f} "
-            f"ms/recon; scan {last + 1}: rel err vs truth {err:.4f} (prior {err_prior:.4f})")
+            f"ms/recon; scan {last + 1}: rel err vs truth {err:.4f} (prior {err_prior:.4f}), "
+            f"needle change error {chg:.3f}")
         del ws, tr
     if "mixed_bf16" in forms:
         f32, bf = forms["fp32"], forms["mixed_bf16"]
@@ -273,6 +293,10 @@ def c2_case_forms(args, cbct, synth, np, torch, dev, stream):
     b = synth.noisy_line_integrals(y.cpu().numpy(), sp["I0"], seed=sp["seed"] + 100)
     b_d = torch.from_numpy(b.astype(np.float32)).to(dev)
     products = sp["n_outer"] * (sp["n_inner"] + 1)
+    err_prior = float(torch.linalg.norm(xprior - cur_d) / torch.linalg.norm(cur_d))
+    # the change against the object the prior was made from: the grown lesion
+    changed = cur_d != base_d
+    d_changed = (cur_d - xprior)[changed]
     out, ref = {}, None
     for name, pr in (("fp32", cbct.PREC_FP32), ("mixed_bf16", cbct.PREC_MIXED_BF16),
                      ("mixed_f16", cbct.PREC_MIXED_F16)):
@@ -291,18 +315,20 @@ def c2_case_forms(args, cbct, synth, np, torch, dev, stream):
         sec = (time.perf_counter() - t) / reps
         if ref is None:
             ref = x.clone()
+        err = float(torch.linalg.norm(x - cur_d) / torch.linalg.norm(cur_d))
         out[name] = {"s_per_recon": round(sec, 4),
                      "gvoxel_proj_s": round(2.0 * products * M * V / sec / 1e9, 2),
-                     "rel_err_vs_truth": round(float(torch.linalg.norm(x - cur_d)
-                                                     / torch.linalg.norm(cur_d)), 5),
+                     "rel_err_vs_truth": round(err, 5),
+                     "improves_on_prior": err < err_prior,
+                     "lesion_change_err": round(float(torch.linalg.norm((x - cur_d)[changed])
+                                                      / torch.linalg.norm(d_changed)), 4),
                      "rel_l2_vs_fp32_gpu": float(torch.linalg.norm(x - ref)
                                                  / torch.linalg.norm(ref))}
         del ws
         log(f"[bench] 256^3 {name}: {sec * 1e3:.1f} ms/recon")
     for k in out:
         out[k]["speedup_vs_fp32"] = round(out["fp32"]["s_per_recon"] / out[k]["s_per_recon"], 3)
-    out["rel_err_prior_vs_truth"] = round(float(torch.linalg.norm(xprior - cur_d)
-                                                / torch.linalg.norm(cur_d)), 5)
+    out["rel_err_prior_vs_truth"] = round(err_prior, 5)
     # FDK of the same scan (direct method, no prior)
     xf = cbct.fdk(g, b_d, stream=stream)
     out["fdk_ms"] = round(time_op(torch, stream, lambda: cbct.fdk(g, b_d, xf, stream=stream),

@@ -45,7 +45,8 @@ _LIB = None
 def _lib():
     global _LIB
     if _LIB is None:
-        path = os.path.join(_HERE, "liboracle.so")
+        # CBCT_ORACLE_LIB selects another build of siddon.c (the sanitizer test)
+        path = os.environ.get("CBCT_ORACLE_LIB") or os.path.join(_HERE, "liboracle.so")
         if not os.path.exists(path):
             from . import build as _build  # noqa: WPS433 (local build helper)
 

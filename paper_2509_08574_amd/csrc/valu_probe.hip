@@ -1,5 +1,5 @@
-// VALU issue-rate probe for gfx950 (measurement helper of bench.py's roofline;
-// not part of the library).
+// VALU issue-rate and vector-memory probe for gfx950 (measurement helper of
+// bench.py's roofline; not part of the library).
 //
 // One kernel per instruction kind, each a long loop of 8 independent chains of
 // that one instruction (written in inline assembly so that the compiler can
@@ -9,6 +9,13 @@
 // classifies each kind as a 2-cycle (dual-issued), 4-cycle or 8-cycle
 // instruction.  Run it under rocprofv3 --pmc SQ_INSTS_VALU SQ_ACTIVE_INST_VALU2
 // to see which kinds the second VALU pipe takes.
+//
+// Two vector-memory kernels follow: coalesced 16-byte loads and 12-byte
+// gathers shaped like the adjoint projector's window reads (lane l reads three
+// floats starting about two rows after lane l - 1), both from an L2-resident
+// buffer.  Run under rocprofv3 --pmc TD_TD_BUSY_sum TA_TA_BUSY_sum
+// GRBM_GUI_ACTIVE to see the texture units' busy fraction reach 1 when loads
+// alone bound a kernel.
 #include <hip/hip_runtime.h>
 
 #include <cstdio>
@@ -58,6 +65,55 @@ __global__ void __launch_bounds__(256) probe(float *out, int iters, float a, flo
 #pragma unroll
     for (int q = 0; q < kChains; ++q) s += f[q] + (float)u[q];
     if (s == 12345.678f) out[blockIdx.x] = s;  // keeps the chains live; never true in practice
+}
+
+// Vector-memory probe: KIND 0 coalesced float4 loads, KIND 1 window gathers of
+// three floats (lane l at row 2l + (l >> 3), the rows of 64 cells' windows), from
+// a buffer of `n` floats that stays in L2; `iters` passes of 64 loads per lane.
+template <int KIND>
+__global__ void __launch_bounds__(256) vmem(const float *__restrict__ buf, int n, int iters,
+                                            float *out) {
+    const int lane = threadIdx.x & 63;
+    const int wave = (blockIdx.x * 4 + (threadIdx.x >> 6));
+    float s = 0.f;
+    for (int it = 0; it < iters; ++it) {
+#pragma unroll 8
+        for (int r = 0; r < 64; ++r) {
+            if constexpr (KIND == 0) {
+                const int o = ((wave * 64 + r) * 256 + lane * 4) & (n - 4);  // 16-byte aligned
+                const float4 v = *(const float4 *)(buf + o);
+                s += v.x + v.y + v.z + v.w;
+            } else {
+                const int o = ((wave * 97 + r * 131) * 4 + 2 * lane + (lane >> 3)) & (n - 4);
+                s += buf[o] + buf[o + 1] + buf[o + 2];
+            }
+        }
+    }
+    if (s == 12345.678f) out[blockIdx.x] = s;  // keeps the loads live; never true in practice
+}
+
+template <int KIND>
+int run_vmem(const float *buf, int n, float *out, int blocks, int iters) {
+    hipEvent_t e0, e1;
+    CHECK(hipEventCreate(&e0));
+    CHECK(hipEventCreate(&e1));
+    hipLaunchKernelGGL(vmem<KIND>, dim3(blocks), dim3(256), 0, 0, buf, n, iters, out);
+    CHECK(hipGetLastError());
+    CHECK(hipDeviceSynchronize());
+    CHECK(hipEventRecord(e0, 0));
+    hipLaunchKernelGGL(vmem<KIND>, dim3(blocks), dim3(256), 0, 0, buf, n, iters, out);
+    CHECK(hipEventRecord(e1, 0));
+    CHECK(hipEventSynchronize(e1));
+    float ms = 0.f;
+    CHECK(hipEventElapsedTime(&ms, e0, e1));
+    const double instr = blocks * 4.0 * iters * 64;
+    const double bytes = instr * 64 * (KIND == 0 ? 16 : 12);
+    std::printf("%-20s %9.3f ms  %8.1f G wave-loads/s  %8.1f GB/s of lane data\n",
+                KIND == 0 ? "load float4" : "gather 3 floats", ms, instr / (ms * 1e-3) / 1e9,
+                bytes / (ms * 1e-3) / 1e9);
+    CHECK(hipEventDestroy(e0));
+    CHECK(hipEventDestroy(e1));
+    return 0;
 }
 
 static const char *kNames[] = {"v_fma_f32", "v_add_f32", "v_mul_f32", "v_add_u32",
@@ -116,6 +172,13 @@ int main() {
     rc |= run<9>(out, blocks, iters, clk);
     rc |= run<10>(out, blocks, iters, clk);
     rc |= run<11>(out, blocks, iters, clk);
+    const int n = 1 << 20;  // 4 MB: resident in L2
+    float *buf = nullptr;
+    CHECK(hipMalloc(&buf, sizeof(float) * n));
+    CHECK(hipMemset(buf, 0, sizeof(float) * n));
+    rc |= run_vmem<0>(buf, n, out, blocks, 40);
+    rc |= run_vmem<1>(buf, n, out, blocks, 40);
+    CHECK(hipFree(buf));
     CHECK(hipFree(out));
     return rc;
 }

@@ -11,7 +11,9 @@ import os
 import numpy as np
 import pytest
 
-LIB = os.path.join(os.path.dirname(__file__), "..", "paper_2509_08574_amd", "libcbct_sim.so")
+# CBCT_SIM_LIB selects another build of serve_sim.cpp (the sanitizer test)
+LIB = os.environ.get("CBCT_SIM_LIB") or os.path.join(os.path.dirname(__file__), "..",
+                                                     "paper_2509_08574_amd", "libcbct_sim.so")
 
 OK, PENDING, ERR_OOM, ERR_DEVICE, ERR_BUSY, ERR_NOT_FOUND = 0, 1, -2, -3, -4, -5
 A = 256  # allocation granule
