@@ -472,6 +472,22 @@ struct Workspace {
 
 static size_t al(size_t b) { return (b + 255) & ~(size_t)255; }
 
+#ifndef CBCT_U16_FOOTPRINT_BYTES
+#define CBCT_U16_FOOTPRINT_BYTES (128 * 1024)
+#endif
+// Whether the mixed forms' adjoint reads a 16-bit copy of u-hat.  The adjoint
+// visits voxel columns in 16 x 16 tiles; per view such a tile sees about
+// 16 h sqrt(2) DSD / (DSO du) + 2 detector columns of nv rows.  When that
+// footprint (float32) is large the tile's reads miss L2 (hit rate 0.88 at 93 KB,
+// 0.51 at 197 KB) and halving the bytes pays; when it is small the 16-bit
+// window read and its widening cost more than the bytes they save.
+static bool adjoint_reads_u16(const cbct_geom *g) {
+    const cbct_geom_desc &d = g->d;
+    const double h = std::max(d.vx, d.vy);
+    const double cols = 16.0 * h * std::sqrt(2.0) * d.dsd / (d.dso * d.du) + 2.0;
+    return cols * d.nv * 4.0 > (double)CBCT_U16_FOOTPRINT_BYTES;
+}
+
 static Workspace carve(const cbct_geom *g, const GeoK &G, const piccs_params *p, char *base) {
     Workspace W{};
     const size_t vb = al(sizeof(float) * (size_t)g->pad_floats());
@@ -497,7 +513,8 @@ static Workspace carve(const cbct_geom *g, const GeoK &G, const piccs_params *p,
     }
     W.bhat = (float *)take(pb);
     W.uhat = (float *)take(pb);
-    if (p->precision != CBCT_PREC_FP32)  // 2 bytes per sample, read up to 8 bytes past the last
+    if (p->precision != CBCT_PREC_FP32 && adjoint_reads_u16(g))
+        // 2 bytes per sample, read up to 8 bytes past the last
         W.uhat16 = (unsigned short *)take(sizeof(unsigned short) * (size_t)g->n_proj() + 8);
     W.pf = (double *)take(sizeof(double) * (size_t)W.nf);
     W.pr = (double *)take(sizeof(double) * (size_t)W.nr);
@@ -621,7 +638,7 @@ void solve_enqueue(cbct_geom *g, const float *b, const float *xp, float *x,
             fa.vol = dt == CBCT_F32 ? (const void *)W.V : (const void *)W.V16;
             fa.uin = W.uhat; fa.s1 = W.sc + SC_FWD_S1; fa.s2 = W.sc + SC_FWD_S2;
             // mixed forms: the inner forward also writes the adjoint's 16-bit input
-            fa.u16 = W.uhat16; fa.u16_dt = dt; fa.u16_scale = W.sc + SC_U16_SCALE;
+            fa.u16 = W.uhat16; fa.u16_dt = dt; fa.u16_scale = W.sc + SC_U16_SCALE;  // or null
             launch_forward(G, FWD_SOLVER, fa, s,
                            dt == CBCT_BF16  ? CBCT_BF16_PAIR
                            : dt == CBCT_F16 ? CBCT_F16_PAIR
@@ -631,10 +648,10 @@ void solve_enqueue(cbct_geom *g, const float *b, const float *xp, float *x,
                                alpha, lam, W.sc + SC_REG_S1, W.sc + SC_REG_S2, W.pr, W.fl);
             hipLaunchKernelGGL(k_red<RED_BETA>, dim3(1), dim3(1024), 0, s, W.pf, W.nf,
                                W.pr, W.nr, W.sc, W.fl, W.hist, it_global, dt, nvox, uref);
-            if (dt == CBCT_F32)
-                launch_back(G, W.uhat, W.t, W.fl, s);
-            else
+            if (W.uhat16)
                 launch_back(G, W.uhat16, W.t, W.fl, s, dt, W.sc + SC_U16_SCALE);
+            else
+                launch_back(G, W.uhat, W.t, W.fl, s);
             hipLaunchKernelGGL(regA, dim3(nvb), dim3(256), 0, s, G, W.t, W.W1, W.W2, W.u1,
                                W.u2, W.cstride, alpha, lam, W.V, W.sc + SC_BACK_S1,
                                W.sc + SC_BACK_S2, W.pa, W.fl);

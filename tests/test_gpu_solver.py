@@ -201,6 +201,38 @@ def test_mixed_precision_solve_within_1e3_of_fp64(orc, lib, prec):
     assert rep["inner_done"] == sp["n_outer"] * sp["n_inner"]
 
 
+# A small volume seen on a tall detector: a 16 x 16 column tile's per-view
+# detector footprint in float32, (16 h sqrt(2) DSD / (DSO du) + 2) x nv x 4 B =
+# 36 x 1024 x 4 B = 147 KB, is past the 128 KB above which the mixed forms' adjoint
+# reads the 16-bit copy of u-hat (at 256^3 it is 91 KB, at 512x512x400 193 KB).
+TALL = dict(nx=20, ny=20, nz=40, vx=1.0, vy=1.0, vz=0.5, nu=24, nv=1024, du=1.0, dv=0.25,
+            dso=400.0, dsd=600.0, n_views=9)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16", "f16"])
+def test_mixed_adjoint_16bit_input_against_oracle(orc, lib, prec):
+    """The adjoint's 16-bit u-hat (bf16, scaled fp16) through a whole IRN-PICCS
+    solve, against the FP64 oracle: 1e-3 for the mixed forms, 1e-4 for FP32."""
+    from paper_2509_08574_amd import synth
+    og = orc.Geometry.from_dict(TALL)
+    prior, _ = synth.ellipsoid_phantom(og.vol_shape, 6, (2.0, 8.0), seed=21)
+    cur = prior.copy()
+    synth.add_cylinder(cur, (10.0, 10.0, 20.0), (0.2, 0.3, 0.9), 1.0, 20.0, 2.0)
+    b = synth.noisy_line_integrals(orc.forward(og, cur), 1e5, seed=22)
+    b = b.astype(np.float32).astype(np.float64)
+    prior = prior.astype(np.float32).astype(np.float64)
+    ref = orc.irn_piccs(og, b, prior, prior, 1.0, 1.0, 0.1, 2, 3)
+    pr = {"fp32": lib.PREC_FP32, "bf16": lib.PREC_MIXED_BF16, "f16": lib.PREC_MIXED_F16}[prec]
+    xg, rep = _gpu_solve(lib, TALL, b, prior, prior, lib.SolveParams(1.0, 1.0, 0.1, 2, 3,
+                                                                    precision=pr))
+    err = rel(xg, ref.x)
+    print(f"tall detector {prec}: rel L2 vs FP64 oracle {err:.2e}")
+    assert rep["inner_done"] == 6 and rep["breakdown"] == 0
+    assert err <= (SOLVE_TOL if prec == "fp32" else 1e-3)
+    np.testing.assert_allclose(rep["phibar"], ref.phibar,
+                               rtol=SOLVE_TOL if prec == "fp32" else 1e-3)
+
+
 def test_mixed_forms_on_ragged_geometry(orc, lib):
     rng = np.random.default_rng(19)
     d = dict(nx=21, ny=19, nz=17, vx=1.0, vy=1.0, vz=1.0, nu=37, nv=150, du=1.1, dv=0.45,
