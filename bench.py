@@ -713,7 +713,7 @@ def c3_precision_bench(args, cbct, synth, np, torch, dev):
         x = xp.clone()
         cbct.solve(g, b, xp, x, p, workspace=ws, report=False)   # warm-up
         torch.cuda.synchronize()
-        reps = 2
+        reps = args.c3_reps
         t = time.perf_counter()
         for _ in range(reps):
             x.copy_(xp)
@@ -791,6 +791,9 @@ def main():
                     help="timed solves per precision form of the 256^3 case")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-c2", action="store_true", help="skip the 256^3 case")
+    ap.add_argument("--no-c3", action="store_true", help="skip the 512^3 precision comparison")
+    ap.add_argument("--c3-reps", type=int, default=1,
+                    help="timed solves per precision form of the 512^3 case")
     ap.add_argument("--fp32-only", action="store_true", help="skip the mixed-precision forms")
     ap.add_argument("--op-reps", type=int, default=10)
     ap.add_argument("--calib-copy-mib", type=int, default=0,
@@ -872,6 +875,7 @@ def main():
     c5 = repeated_scans(args, cbct, synth, np, torch, dev, stream)
     f32 = c5["forms"]["fp32"]
     c2 = None if args.no_c2 else c2_case_forms(args, cbct, synth, np, torch, dev, stream)
+    c3 = None if args.no_c3 else c3_precision_bench(args, cbct, synth, np, torch, dev)
     cpu, errs = (None, {}) if args.no_cpu else cpu_baseline_and_oracle_errors(
         args, cbct, synth, np, torch, dev, c5)
     forms = c5["forms"]
@@ -913,6 +917,8 @@ def main():
         # every form against the FP64 oracle on reduced problems (labelled by case)
         "precision_vs_fp64_oracle": errs,
         "c2": c2,
+        # 512^3 at 0.5 mm, 1024 x 768 at 0.4 mm, 120 views, 5 x 10: the three forms
+        "c3_512": c3,
         "serving": serving,
         "roofline": c5["roofline"],
         "cpu_baseline": cpu,
