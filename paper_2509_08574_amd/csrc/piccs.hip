@@ -46,24 +46,34 @@ struct VoxIdx {
     int64_t c;  // index relative to the padded base P
 };
 
+// Tiles of 64 cells along z by 4 columns along x, one wave per column.  The
+// dispatcher hands block b to XCD b mod 8 and each XCD runs its blocks roughly
+// in order, so the mapping below gives XCD x the x-th contiguous eighth (a slab
+// of S tiles) of every y-plane, plane after plane.  A tile's z and x neighbours
+// then lie in the same slab, and its y neighbour one slab later, on the same XCD:
+// the cache lines two tiles share (columns start 4 bytes past a line, and Z is
+// not a multiple of 32) are fetched into one L2, not into two.
 __device__ __forceinline__ VoxIdx vox_index(const GeoK &G) {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int nkb = (G.nz + 63) >> 6, nxb = (G.nx + 3) >> 2;
-    const unsigned b = blockIdx.x;
-    const int kb = (int)(b % (unsigned)nkb);
-    const unsigned t = b / (unsigned)nkb;
-    const int ib = (int)(t % (unsigned)nxb);
+    const unsigned nkb = (unsigned)(G.nz + 63) >> 6, nxb = (unsigned)(G.nx + 3) >> 2;
+    const unsigned P = nkb * nxb, S = (P + 7) >> 3;
+    const unsigned b = blockIdx.x, s = b >> 3;
+    const unsigned j = s / S;
+    const unsigned p = (b & 7) * S + (s - j * S);  // tile within plane j
     VoxIdx v;
-    v.j = (int)(t / (unsigned)nxb);
-    v.i = ib * 4 + w;
-    v.k = kb * 64 + lane;
-    v.ok = v.i < G.nx && v.k < G.nz;
+    v.j = (int)j;
+    v.i = (int)(p / nkb) * 4 + w;
+    v.k = (int)(p % nkb) * 64 + lane;
+    v.ok = p < P && v.i < G.nx && v.k < G.nz;
     v.c = ((int64_t)v.j * G.nx + v.i) * G.Z + v.k + 1;
     return v;
 }
 
+// Blocks of a launch over the volume: 8 slabs of S tiles per y-plane (the last
+// slab may hold up to 7 idle tiles, which still write a zero partial).
 static int64_t vox_blocks(const GeoK &G) {
-    return (int64_t)((G.nz + 63) / 64) * ((G.nx + 3) / 4) * G.ny;
+    const int64_t P = (int64_t)((G.nz + 63) / 64) * ((G.nx + 3) / 4);
+    return 8 * ((P + 7) / 8) * G.ny;
 }
 
 // Sum of `v` over the block (256 threads), written to part[blockIdx.x].

@@ -16,6 +16,12 @@
 // buffer.  Run under rocprofv3 --pmc TD_TD_BUSY_sum TA_TA_BUSY_sum
 // GRBM_GUI_ACTIVE to see the texture units' busy fraction reach 1 when loads
 // alone bound a kernel.
+//
+// Last, HBM streams over arrays far larger than the caches (4 MB of L2 per XCD,
+// 256 MB last-level cache), one element per thread in 256-thread blocks as the
+// volume stencils run: a plain copy, a float4 copy, and R reads + 1 write per
+// element for the read/write mixes of the stencils.  They give the bandwidth a
+// streaming kernel reaches in practice, beside the 8 TB/s of the data sheet.
 #include <hip/hip_runtime.h>
 
 #include <cstdio>
@@ -90,6 +96,85 @@ __global__ void __launch_bounds__(256) vmem(const float *__restrict__ buf, int n
         }
     }
     if (s == 12345.678f) out[blockIdx.x] = s;  // keeps the loads live; never true in practice
+}
+
+template <int R>
+struct Ptrs {
+    const float *p[R];
+};
+
+// out[t] = sum of the R inputs at t: R reads and one write per element.
+template <int R>
+__global__ void __launch_bounds__(256) stream_mix(Ptrs<R> in, float *__restrict__ out,
+                                                  long long n) {
+    const long long t = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (t >= n) return;
+    float s = 0.f;
+#pragma unroll
+    for (int q = 0; q < R; ++q) s += in.p[q][t];
+    out[t] = s;
+}
+
+__global__ void __launch_bounds__(256) stream_copy4(const float4 *__restrict__ a,
+                                                    float4 *__restrict__ b, long long n4) {
+    const long long t = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (t < n4) b[t] = a[t];
+}
+
+// `arrs` holds R + 1 arrays of n floats each: R inputs, then the output.
+template <int R>
+int run_stream(float *const *arrs, long long n) {
+    Ptrs<R> in;
+    for (int q = 0; q < R; ++q) in.p[q] = arrs[q];
+    float *out = arrs[R];
+    const unsigned blocks = (unsigned)((n + 255) / 256);
+    hipEvent_t e0, e1;
+    CHECK(hipEventCreate(&e0));
+    CHECK(hipEventCreate(&e1));
+    hipLaunchKernelGGL(stream_mix<R>, dim3(blocks), dim3(256), 0, 0, in, out, n);
+    CHECK(hipGetLastError());
+    CHECK(hipDeviceSynchronize());
+    const int reps = 5;
+    CHECK(hipEventRecord(e0, 0));
+    for (int r = 0; r < reps; ++r)
+        hipLaunchKernelGGL(stream_mix<R>, dim3(blocks), dim3(256), 0, 0, in, out, n);
+    CHECK(hipEventRecord(e1, 0));
+    CHECK(hipEventSynchronize(e1));
+    float ms = 0.f;
+    CHECK(hipEventElapsedTime(&ms, e0, e1));
+    ms /= reps;
+    const double bytes = (R + 1) * 4.0 * (double)n;
+    std::printf("stream %2d read + 1 write %9.3f ms  %8.1f GB/s  (%lld floats per array)\n", R, ms,
+                bytes / (ms * 1e-3) / 1e9, n);
+    CHECK(hipEventDestroy(e0));
+    CHECK(hipEventDestroy(e1));
+    return 0;
+}
+
+int run_copy4(float *a, float *b, long long n) {
+    const long long n4 = n / 4;
+    const unsigned blocks = (unsigned)((n4 + 255) / 256);
+    hipEvent_t e0, e1;
+    CHECK(hipEventCreate(&e0));
+    CHECK(hipEventCreate(&e1));
+    hipLaunchKernelGGL(stream_copy4, dim3(blocks), dim3(256), 0, 0, (const float4 *)a, (float4 *)b, n4);
+    CHECK(hipGetLastError());
+    CHECK(hipDeviceSynchronize());
+    const int reps = 5;
+    CHECK(hipEventRecord(e0, 0));
+    for (int r = 0; r < reps; ++r)
+        hipLaunchKernelGGL(stream_copy4, dim3(blocks), dim3(256), 0, 0, (const float4 *)a,
+                           (float4 *)b, n4);
+    CHECK(hipEventRecord(e1, 0));
+    CHECK(hipEventSynchronize(e1));
+    float ms = 0.f;
+    CHECK(hipEventElapsedTime(&ms, e0, e1));
+    ms /= reps;
+    std::printf("stream float4 copy        %9.3f ms  %8.1f GB/s  (%lld floats per array)\n", ms,
+                8.0 * (double)n / (ms * 1e-3) / 1e9, n);
+    CHECK(hipEventDestroy(e0));
+    CHECK(hipEventDestroy(e1));
+    return 0;
 }
 
 template <int KIND>
@@ -180,5 +265,18 @@ int main() {
     rc |= run_vmem<1>(buf, n, out, blocks, 40);
     CHECK(hipFree(buf));
     CHECK(hipFree(out));
+    // 11 arrays of 2^27 floats (512 MB each, 5.6 GB in all)
+    const long long ns = 1ll << 27;
+    float *arrs[11];
+    for (int q = 0; q < 11; ++q) {
+        CHECK(hipMalloc(&arrs[q], sizeof(float) * ns));
+        CHECK(hipMemset(arrs[q], 0, sizeof(float) * ns));
+    }
+    rc |= run_copy4(arrs[0], arrs[1], ns);
+    rc |= run_stream<1>(arrs, ns);
+    rc |= run_stream<2>(arrs, ns);
+    rc |= run_stream<4>(arrs, ns);
+    rc |= run_stream<10>(arrs, ns);
+    for (int q = 0; q < 11; ++q) CHECK(hipFree(arrs[q]));
     return rc;
 }
