@@ -116,6 +116,19 @@ int cbct_back(const cbct_geom *g, const void *y, cbct_dtype yt, float y_scale, f
               void *hip_stream);
 
 /*
+ * Views per launch of A^T for geometry g (a tuning knob; 0 = automatic, the
+ * default).  cbct_back, cbct_back_cols and the solvers run A^T as one launch per
+ * chunk of consecutive views; each launch continues the cells' float32 partial
+ * sums left in the output by the one before.  Short chunks keep the detector
+ * data that the blocks resident on one XCD read within that XCD's L2; the
+ * automatic choice bounds one 16 x 16-column tile's detector footprint over a
+ * chunk at about 3.5 MB.  Every chunk size gives the same results bit for bit.
+ * Takes effect on the next call with g; not to be called while another thread
+ * uses g.  Errors: CBCT_ERR_INVALID (null g, views < 0).
+ */
+int cbct_geom_set_back_views(cbct_geom *g, int views);
+
+/*
  * Allocation-free cbct_forward, for callers that cannot allocate device memory:
  * code under HIP graph capture, tight serving loops, harnesses that forbid
  * hipMalloc.  Same operation, arguments, layouts and results as cbct_forward

@@ -34,7 +34,8 @@ EXPORTS = ["cbct_last_error", "cbct_geom_create", "cbct_geom_destroy", "cbct_geo
            "cbct_cols_to_vol", "cbct_proj_to_cols", "cbct_cols_to_proj", "cbct_forward_cols",
            "cbct_back_cols", "cbct_server_create", "cbct_server_add_prior", "cbct_server_submit",
            "cbct_server_poll", "cbct_server_stats_get", "cbct_server_destroy",
-           "cbct_server_footprint", "cbct_fdk", "cbct_forward_noalloc"]
+           "cbct_server_footprint", "cbct_fdk", "cbct_forward_noalloc",
+           "cbct_geom_set_back_views"]
 
 
 class GeomDesc(ctypes.Structure):
@@ -69,6 +70,7 @@ _lib.cbct_geom_destroy.restype = None
 _lib.cbct_geom_sizes.argtypes = [_vp, ctypes.POINTER(ctypes.c_int64),
                                  ctypes.POINTER(ctypes.c_int64)]
 _lib.cbct_geom_nnz.argtypes = [_vp, ctypes.POINTER(ctypes.c_int64), _vp]
+_lib.cbct_geom_set_back_views.argtypes = [_vp, ctypes.c_int]
 _lib.cbct_forward.argtypes = [_vp, _vp, ctypes.c_int, ctypes.c_float, _vp, _vp]
 _lib.cbct_back.argtypes = [_vp, _vp, ctypes.c_int, ctypes.c_float, _vp, _vp]
 _lib.cbct_forward_noalloc.argtypes = [_vp, _vp, ctypes.c_int, ctypes.c_float, _vp, _vp]
@@ -161,6 +163,10 @@ class Geometry:
         v = ctypes.c_int64()
         _check(_lib.cbct_geom_nnz(self.handle, ctypes.byref(v), _stream(stream)))
         return v.value
+
+    def set_back_views(self, views):
+        """Views per launch of A^T (0 = automatic); results are the same bits."""
+        _check(_lib.cbct_geom_set_back_views(self.handle, int(views)))
 
     def close(self):
         if getattr(self, "handle", None):

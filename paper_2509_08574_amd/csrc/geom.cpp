@@ -151,6 +151,7 @@ static GeoK make_geok(const cbct_geom *g, const DevTables &t) {
     G.xy = t.xy; G.xy0 = t.xy0; G.zr = t.zr; G.Lu2 = t.Lu2; G.Lv2 = t.Lv2; G.trig = t.trig;
     G.seghdr = t.seghdr; G.seg = t.seg; G.seg_stride = d.nx + d.ny - 1 + kSegPad;
     G.fdkw = t.fdkw; G.ramp = t.ramp;
+    G.back_views = g->back_views;
     return G;
 }
 
@@ -325,6 +326,15 @@ void cbct_geom_destroy(cbct_geom *g) {
     }
     (void)hipSetDevice(cur);
     delete g;
+}
+
+int cbct_geom_set_back_views(cbct_geom *g, int views) {
+    if (!g || views < 0) {
+        set_last_error(!g ? "null geometry" : "views per adjoint launch must be >= 0");
+        return CBCT_ERR_INVALID;
+    }
+    g->back_views = views;
+    return CBCT_OK;
 }
 
 int cbct_geom_sizes(const cbct_geom *g, int64_t *n_vox, int64_t *n_proj) {

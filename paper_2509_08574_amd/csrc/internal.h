@@ -73,6 +73,7 @@ struct GeoK {
     // ramp[0] = 1/(4 dp) (tap 0), ramp[m+1] = -1/((2m+1)^2 pi^2 dp) (taps +-(2m+1)).
     const float *fdkw;   // [nviews]
     const float *ramp;   // [nu/2 + 1]
+    int back_views;      // views per launch of A^T; 0 = chosen from the geometry
 };
 
 constexpr int kSegPad = 4;
@@ -106,6 +107,7 @@ struct cbct_geom {
     std::vector<float> fdkw, ramp;
     std::mutex mu;
     std::map<int, cbct::DevTables> dev;
+    int back_views = 0;  // cbct_geom_set_back_views (0 = automatic)
 
     int64_t n_vox() const { return (int64_t)d.nx * d.ny * d.nz; }
     int64_t n_proj() const { return (int64_t)d.n_views * d.nv * d.nu; }

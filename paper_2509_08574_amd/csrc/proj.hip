@@ -16,7 +16,8 @@
 // cross (i, j) and recomputes the forward walk's x-y interval [aa, ab]; each
 // lane then gathers, for each of its cells, a short window of detector rows
 // whose chords with that cell are the forward kernel's c0 / c1 bit for bit.
-// Every cell is summed in a fixed order and written once; no atomics.
+// The views run in chunks of one launch each (back_views_per_launch); every
+// cell is summed over the views in a fixed order, with no atomics.
 #include <hip/hip_bf16.h>
 #include <hip/hip_fp16.h>
 
@@ -528,7 +529,7 @@ template <int C, int DT>
 __global__ void __launch_bounds__(256)
 k_back(GeoK G, const void *__restrict__ yin, float *__restrict__ out, const int *brk,
        const double *in_scale, float a_ref, float z_lo_mm, float fv_off, float fu_margin,
-       int kspan, int nq) {
+       int kspan, int nq, int v0, int v1) {
     if (brk && *brk == 2) return;
     using YT = typename BackIn<DT>::T;
     const YT *yhat = (const YT *)yin;
@@ -563,9 +564,11 @@ k_back(GeoK G, const void *__restrict__ yin, float *__restrict__ out, const int 
     bool kok[QM];
 #pragma unroll
     for (int q = 0; q < QM; ++q) {
-        acc[q] = 0.0f;
         const int k = kbase + lane + 64 * q;
         kok[q] = q < nq && k < G.nz;
+        // views v0 .. v1 - 1 continue the sums of the views before v0 (unscaled
+        // float32 partial sums stored by the previous launch)
+        acc[q] = v0 > 0 && kok[q] ? out[(size_t)col * G.Z + k + 1] : 0.0f;
         fk[q] = (float)(k - (G.nz >> 1));      // plane index relative to nz / 2
         fk1[q] = fk[q] + 1.0f;
         zk0[q] = fmaf((float)k, G.hz, z_lo_mm);   // cell's lower z [mm]
@@ -585,8 +588,8 @@ k_back(GeoK G, const void *__restrict__ yin, float *__restrict__ out, const int 
     // 64 views lane t computes it for view view + t, and each view then reads
     // its own back with readlane instead of all 64 lanes recomputing it.
     int fu0v = 0, fu1v = -1;
-    for (int view = 0; view < G.nviews; ++view) {
-        const int tv = view & 63;
+    for (int view = v0; view < v1; ++view) {
+        const int tv = (view - v0) & 63;
         if (tv == 0) {
             // detector u range of the column's x-y square: a ray with a positive
             // chord crosses the square's interior, so its pixel lies strictly between
@@ -595,7 +598,7 @@ k_back(GeoK G, const void *__restrict__ yin, float *__restrict__ out, const int 
             const int vw = view + lane;
             fu0v = 0;
             fu1v = -1;
-            if (vw < G.nviews) {
+            if (vw < v1) {
                 const float2 cs = G.trig[vw];
                 float umin = 3.0e38f, umax = -3.0e38f;
 #pragma unroll
@@ -663,8 +666,9 @@ k_back(GeoK G, const void *__restrict__ yin, float *__restrict__ out, const int 
         }
     }
     float *oc = out + (size_t)col * G.Z;
-    // a scaled 16-bit input carries the power-of-two scale: divide it out (exact)
-    const float inv = DT == CBCT_F16 ? (float)(1.0 / *in_scale) : 1.0f;
+    // a scaled 16-bit input carries the power-of-two scale: the last launch
+    // divides it out (exact)
+    const float inv = DT == CBCT_F16 && v1 == G.nviews ? (float)(1.0 / *in_scale) : 1.0f;
 #pragma unroll
     for (int q = 0; q < QM; ++q)
         if (kok[q]) oc[kbase + lane + 64 * q + 1] = DT == CBCT_F16 ? acc[q] * inv : acc[q];
@@ -702,6 +706,31 @@ static int back_candidates(const GeoK &G) {
     return (int)std::floor(span * 1.02 + 0.01) + 1;
 }
 
+// Views per launch of A^T.  A block sums its cells over the views in order, and
+// the blocks resident on one XCD (about 224, i.e. 3.5 tiles of 16 x 16 columns)
+// are spread over the views they have reached: blocks finish and are replaced
+// at different times.  Over all views, the detector data those blocks touch
+// overflows the XCD's 4 MB L2 at the larger geometries (hit rate 0.50 at
+// 512 x 512 x 400 with 180 views).  One launch per chunk of views bounds that
+// spread.  The chunk is sized so that one tile's detector footprint per view
+// (the detector columns a 16-column tile can cast its shadow on, times the rows
+// a voxel column spans) over the chunk's views stays near 3.5 MB.  A
+// cell's float32 partial sum passes from launch to launch through the output,
+// unchanged, so every chunk size gives the same bits.  Measured per A^T (views
+// per launch: ms): 512 x 512 x 400, 180 views: all 49.0, 45: 41.5, 20: 40.2,
+// 12: 41.3, 8: 43.9; 256^3, 90 views: all 2.81, 45: 2.74, 20: 2.78, 12: 2.91.
+static int back_views_per_launch(const GeoK &G, size_t sample_bytes) {
+    if (G.back_views > 0) return std::min(G.back_views, G.nviews);
+    const double h = std::max(G.hx, G.hy), mag = (double)G.dsd / G.dso;
+    const double cols = 16.0 * h * std::sqrt(2.0) * mag / G.du + 2.0;
+    const double rows = std::min((double)G.nv, G.nz * (double)G.hz * mag / G.dv);
+    const double per_view = cols * rows * (double)sample_bytes;
+    const int v = std::max(8, (int)(3.5e6 / per_view));
+    if (v >= G.nviews) return G.nviews;
+    const int chunks = (G.nviews + v - 1) / v;
+    return (G.nviews + chunks - 1) / chunks;  // equal chunks
+}
+
 template <int DT>
 static void launch_back_dt(const GeoK &G, const void *yhat, float *out, const int *brk,
                            const double *scale, hipStream_t s) {
@@ -721,9 +750,12 @@ static void launch_back_dt(const GeoK &G, const void *yhat, float *out, const in
     const float fu_margin = (float)back_margin_cols(G.nu);
     // window of C rows; never more rows than the detector has
     const int C = std::min(back_candidates(G), G.nv);
+    const int vc = back_views_per_launch(G, sizeof(typename BackIn<DT>::T));
     auto go = [&](auto kern) {
-        hipLaunchKernelGGL(kern, dim3((unsigned)nb), dim3(256), shm, s, G, yhat, out, brk, scale,
-                           a_ref, z_lo_mm, fv_off, fu_margin, kspan, nq);
+        for (int v0 = 0; v0 < G.nviews; v0 += vc)
+            hipLaunchKernelGGL(kern, dim3((unsigned)nb), dim3(256), shm, s, G, yhat, out, brk,
+                               scale, a_ref, z_lo_mm, fv_off, fu_margin, kspan, nq, v0,
+                               std::min(G.nviews, v0 + vc));
     };
     switch (C) {
         case 1: go(k_back<1, DT>); break;

@@ -254,6 +254,30 @@ def test_dtype_inputs(orc, lib):
             assert rel(xg, orc.back(og, yr)) <= TOL
 
 
+def test_adjoint_view_chunks_same_bits(orc, lib):
+    """A^T run as one launch per chunk of views, the cells' partial sums carried
+    through the output, gives the bits of a single launch: float32 and 16-bit
+    inputs (the fp16 scale is divided out by the last launch only), chunks of one
+    view, a ragged last chunk, and chunks longer than the scan; and it matches
+    the oracle."""
+    import torch
+    og, gg = _geoms(orc, lib, "rows")  # 9 views: one launch when automatic
+    rng = np.random.default_rng(12)
+    y = rng.uniform(size=og.proj_shape)
+    for dt, sc in ((torch.float32, 1.0), (torch.bfloat16, 2.0), (torch.float16, 0.25)):
+        ys = torch.from_numpy(y).to(dt).cuda()
+        gg.set_back_views(0)
+        ref = lib.back(gg, ys, y_scale=sc)
+        for v in (1, 2, 4, 8, 9, 50):
+            gg.set_back_views(v)
+            assert torch.equal(lib.back(gg, ys, y_scale=sc), ref), (dt, v)
+        yr = ys.float().cpu().numpy().astype(np.float64) * sc
+        assert rel(host(ref), orc.back(og, yr)) <= TOL
+    gg.set_back_views(0)
+    with pytest.raises(Exception):
+        gg.set_back_views(-1)
+
+
 def test_deterministic(lib):
     from paper_2509_08574_amd import synth
     gg = lib.Geometry.from_dict(synth.geometry("c1"))

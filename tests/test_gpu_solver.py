@@ -233,6 +233,26 @@ def test_mixed_adjoint_16bit_input_against_oracle(orc, lib, prec):
                                rtol=SOLVE_TOL if prec == "fp32" else 1e-3)
 
 
+@pytest.mark.parametrize("prec", ["fp32", "f16"])
+def test_solve_with_adjoint_view_chunks_same_bits(lib, prec):
+    """A whole solve with A^T in chunks of 2 views (the 16-bit u-hat path for the
+    mixed form on this geometry) returns the bits of the automatic choice."""
+    import torch
+    rng = np.random.default_rng(23)
+    gg = lib.Geometry.from_dict(TALL)
+    b = dev(rng.uniform(size=gg.proj_shape) * 5.0)
+    xp = dev(rng.uniform(size=gg.vol_shape))
+    pr = {"fp32": lib.PREC_FP32, "f16": lib.PREC_MIXED_F16}[prec]
+    p = lib.SolveParams(1.0, 1.0, 0.1, 2, 3, precision=pr)
+    outs = []
+    for v in (0, 2):
+        gg.set_back_views(v)
+        x, rep = lib.solve(gg, b, xp, xp.clone(), p)
+        assert rep["inner_done"] == 6
+        outs.append(x)
+    assert torch.equal(outs[0], outs[1])
+
+
 def test_mixed_forms_on_ragged_geometry(orc, lib):
     rng = np.random.default_rng(19)
     d = dict(nx=21, ny=19, nz=17, vx=1.0, vy=1.0, vz=1.0, nu=37, nv=150, du=1.1, dv=0.45,
