@@ -216,8 +216,13 @@ int cbct_fdk(const cbct_geom *g, const float *y, float *x, void *hip_stream);
 
 typedef enum {
     CBCT_PREC_FP32 = 0,       /* float32 storage and projector arithmetic           */
-    CBCT_PREC_MIXED_BF16 = 1, /* bf16 projector operands, fp32 accumulation          */
-    CBCT_PREC_MIXED_F16 = 2   /* scaled fp16 projector operands, fp32 accumulation   */
+    CBCT_PREC_MIXED_BF16 = 1, /* bf16 operand of A (the LSQR vector v), fp32         */
+                              /* accumulation; A^T reads float32                    */
+    CBCT_PREC_MIXED_F16 = 2,  /* scaled fp16 operand of A, fp32 accumulation         */
+    CBCT_PREC_MIXED_BF16_ADJ16 = 3, /* as MIXED_BF16, and A^T reads a bf16 copy of   */
+                                    /* its operand u-hat as well                     */
+    CBCT_PREC_MIXED_F16_ADJ16 = 4   /* as MIXED_F16, and A^T reads a scaled fp16     */
+                                    /* copy of u-hat as well                         */
 } cbct_precision;
 
 /* The prior term (Sec. 2.1): PICCS penalises TV(x - x_p) (eq. "PICCS problem",

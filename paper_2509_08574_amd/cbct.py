@@ -20,6 +20,7 @@ OK, PENDING = 0, 1
 ERR_INVALID, ERR_OOM, ERR_DEVICE, ERR_BUSY, ERR_NOT_FOUND, ERR_NUMERIC = -1, -2, -3, -4, -5, -6
 F32, BF16, F16 = 0, 1, 2
 PREC_FP32, PREC_MIXED_BF16, PREC_MIXED_F16 = 0, 1, 2
+PREC_MIXED_BF16_ADJ16, PREC_MIXED_F16_ADJ16 = 3, 4
 METHOD_PICCS, METHOD_PIPLE = 0, 1
 
 if not os.path.exists(LIB_PATH):

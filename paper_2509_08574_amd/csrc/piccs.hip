@@ -482,20 +482,14 @@ struct Workspace {
 
 static size_t al(size_t b) { return (b + 255) & ~(size_t)255; }
 
-#ifndef CBCT_U16_FOOTPRINT_BYTES
-#define CBCT_U16_FOOTPRINT_BYTES (128 * 1024)
-#endif
-// Whether the mixed forms' adjoint reads a 16-bit copy of u-hat.  The adjoint
-// visits voxel columns in 16 x 16 tiles; per view such a tile sees about
-// 16 h sqrt(2) DSD / (DSO du) + 2 detector columns of nv rows.  When that
-// footprint (float32) is large the tile's reads miss L2 (hit rate 0.88 at 93 KB,
-// 0.51 at 197 KB) and halving the bytes pays; when it is small the 16-bit
-// window read and its widening cost more than the bytes they save.
-static bool adjoint_reads_u16(const cbct_geom *g) {
-    const cbct_geom_desc &d = g->d;
-    const double h = std::max(d.vx, d.vy);
-    const double cols = 16.0 * h * std::sqrt(2.0) * d.dsd / (d.dso * d.du) + 2.0;
-    return cols * d.nv * 4.0 > (double)CBCT_U16_FOOTPRINT_BYTES;
+// Whether A^T reads a 16-bit copy of u-hat (the *_ADJ16 forms).  The default
+// mixed forms read float32: with A^T's view chunks its L2 hit rate is 0.94, and
+// the 16-bit window read and its widening then cost more than the bytes they
+// save (512 x 512 x 400: A^T 41.3 ms from float32, 42.0 ms from bf16 at its best
+// chunk; 256^3: 2.82 against 2.94 ms).
+static bool adjoint_reads_u16(const piccs_params *p) {
+    return p->precision == CBCT_PREC_MIXED_BF16_ADJ16 ||
+           p->precision == CBCT_PREC_MIXED_F16_ADJ16;
 }
 
 static Workspace carve(const cbct_geom *g, const GeoK &G, const piccs_params *p, char *base) {
@@ -523,7 +517,7 @@ static Workspace carve(const cbct_geom *g, const GeoK &G, const piccs_params *p,
     }
     W.bhat = (float *)take(pb);
     W.uhat = (float *)take(pb);
-    if (p->precision != CBCT_PREC_FP32 && adjoint_reads_u16(g))
+    if (adjoint_reads_u16(p))
         // 2 bytes per sample, read up to 8 bytes past the last
         W.uhat16 = (unsigned short *)take(sizeof(unsigned short) * (size_t)g->n_proj() + 8);
     W.pf = (double *)take(sizeof(double) * (size_t)W.nf);
@@ -549,8 +543,7 @@ void check_solve_params(const piccs_params *p) {
                  "alpha, lambda, tau must be finite and >= 0");
     CBCT_REQUIRE(p->n_outer >= 1 && p->n_inner >= 1 && p->n_outer <= 100000 &&
                      p->n_inner <= 100000, "n_outer and n_inner must be >= 1");
-    CBCT_REQUIRE(p->precision == CBCT_PREC_FP32 || p->precision == CBCT_PREC_MIXED_BF16 ||
-                     p->precision == CBCT_PREC_MIXED_F16,
+    CBCT_REQUIRE(p->precision >= CBCT_PREC_FP32 && p->precision <= CBCT_PREC_MIXED_F16_ADJ16,
                  "unknown precision");
     CBCT_REQUIRE(p->reorth == 0 || p->reorth == 1, "reorth must be 0 or 1");
     CBCT_REQUIRE(p->method == CBCT_METHOD_PICCS || p->method == CBCT_METHOD_PIPLE,
@@ -579,9 +572,12 @@ void solve_enqueue(cbct_geom *g, const float *b, const float *xp, float *x,
 
     // padded column copies of the inputs (pads and guards zero)
     launch_fill(W.x - kGuard, W.cstride * 13, 0.0f, s);
-    const int dt = p->precision == CBCT_PREC_MIXED_BF16   ? CBCT_BF16
-                   : p->precision == CBCT_PREC_MIXED_F16 ? CBCT_F16
-                                                          : CBCT_F32;
+    const int dt = p->precision == CBCT_PREC_MIXED_BF16 ||
+                           p->precision == CBCT_PREC_MIXED_BF16_ADJ16
+                       ? CBCT_BF16
+                   : p->precision == CBCT_PREC_MIXED_F16 || p->precision == CBCT_PREC_MIXED_F16_ADJ16
+                       ? CBCT_F16
+                       : CBCT_F32;
     if (dt != CBCT_F32) launch_fill((float *)W.V16buf, (int64_t)(W.v16_bytes / 4), 0.0f, s);
     const double nvox = (double)g->n_vox();
     const double uref = std::sqrt((double)g->n_proj()) / g->d.dsd;

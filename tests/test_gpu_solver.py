@@ -222,7 +222,8 @@ def test_mixed_adjoint_16bit_input_against_oracle(orc, lib, prec):
     b = b.astype(np.float32).astype(np.float64)
     prior = prior.astype(np.float32).astype(np.float64)
     ref = orc.irn_piccs(og, b, prior, prior, 1.0, 1.0, 0.1, 2, 3)
-    pr = {"fp32": lib.PREC_FP32, "bf16": lib.PREC_MIXED_BF16, "f16": lib.PREC_MIXED_F16}[prec]
+    pr = {"fp32": lib.PREC_FP32, "bf16": lib.PREC_MIXED_BF16_ADJ16,
+          "f16": lib.PREC_MIXED_F16_ADJ16}[prec]
     xg, rep = _gpu_solve(lib, TALL, b, prior, prior, lib.SolveParams(1.0, 1.0, 0.1, 2, 3,
                                                                     precision=pr))
     err = rel(xg, ref.x)
@@ -242,7 +243,7 @@ def test_solve_with_adjoint_view_chunks_same_bits(lib, prec):
     gg = lib.Geometry.from_dict(TALL)
     b = dev(rng.uniform(size=gg.proj_shape) * 5.0)
     xp = dev(rng.uniform(size=gg.vol_shape))
-    pr = {"fp32": lib.PREC_FP32, "f16": lib.PREC_MIXED_F16}[prec]
+    pr = {"fp32": lib.PREC_FP32, "f16": lib.PREC_MIXED_F16_ADJ16}[prec]
     p = lib.SolveParams(1.0, 1.0, 0.1, 2, 3, precision=pr)
     outs = []
     for v in (0, 2):

@@ -15,7 +15,8 @@ Each precision form is compared with the same oracle result (paper Sec. 2.2.2:
 LSQR on the augmented system; reading R25: relative L2 of the final x against
 the oracle's final x after the same iterations): FP32 storage within 1e-4
 (float32 rounding through a short Krylov recurrence), the mixed BF16 / scaled
-FP16 forms within 1e-3 (the precision bar).  The phi-bar histories are compared
+FP16 forms, with and without the 16-bit copy of u-hat read by A^T, within 1e-3
+(the precision bar).  The phi-bar histories are compared
 with the same tolerances.  Inputs are float32-rounded on both sides.
 """
 import time
@@ -25,7 +26,8 @@ import pytest
 
 pytestmark = pytest.mark.gpu
 
-TOL = {"fp32": 1e-4, "mixed_bf16": 1e-3, "mixed_f16": 1e-3}
+TOL = {"fp32": 1e-4, "mixed_bf16": 1e-3, "mixed_f16": 1e-3, "mixed_bf16_adj16": 1e-3,
+       "mixed_f16_adj16": 1e-3}
 
 
 @pytest.fixture(scope="module")
@@ -39,7 +41,8 @@ def lib():
 
 def _prec(lib, name):
     return {"fp32": lib.PREC_FP32, "mixed_bf16": lib.PREC_MIXED_BF16,
-            "mixed_f16": lib.PREC_MIXED_F16}[name]
+            "mixed_f16": lib.PREC_MIXED_F16, "mixed_bf16_adj16": lib.PREC_MIXED_BF16_ADJ16,
+            "mixed_f16_adj16": lib.PREC_MIXED_F16_ADJ16}[name]
 
 
 def _rel(a, b):
@@ -108,7 +111,8 @@ def _get(cases, orc, name):
 
 @pytest.mark.timeout(900)
 @pytest.mark.parametrize("name", ["c2", "c5_12views"])
-@pytest.mark.parametrize("form", ["fp32", "mixed_bf16", "mixed_f16"])
+@pytest.mark.parametrize("form", ["fp32", "mixed_bf16", "mixed_f16", "mixed_bf16_adj16",
+                                  "mixed_f16_adj16"])
 def test_full_size_solve_matches_fp64_oracle(orc, lib, cases, name, form):
     import torch
     c = _get(cases, orc, "c2" if name == "c2" else "c5")
