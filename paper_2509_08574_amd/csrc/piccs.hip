@@ -53,6 +53,9 @@ struct VoxIdx {
 // then lie in the same slab, and its y neighbour one slab later, on the same XCD:
 // the cache lines two tiles share (columns start 4 bytes past a line, and Z is
 // not a multiple of 32) are fetched into one L2, not into two.
+// With NP = 2 each thread takes the cell in plane j and the one in plane j + 1
+// (j even), and "plane" above means such a pair of planes.
+template <int NP = 1>
 __device__ __forceinline__ VoxIdx vox_index(const GeoK &G) {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const unsigned nkb = (unsigned)(G.nz + 63) >> 6, nxb = (unsigned)(G.nx + 3) >> 2;
@@ -61,7 +64,7 @@ __device__ __forceinline__ VoxIdx vox_index(const GeoK &G) {
     const unsigned j = s / S;
     const unsigned p = (b & 7) * S + (s - j * S);  // tile within plane j
     VoxIdx v;
-    v.j = (int)j;
+    v.j = (int)j * NP;
     v.i = (int)(p / nkb) * 4 + w;
     v.k = (int)(p % nkb) * 64 + lane;
     v.ok = p < P && v.i < G.nx && v.k < G.nz;
@@ -71,9 +74,10 @@ __device__ __forceinline__ VoxIdx vox_index(const GeoK &G) {
 
 // Blocks of a launch over the volume: 8 slabs of S tiles per y-plane (the last
 // slab may hold up to 7 idle tiles, which still write a zero partial).
+template <int NP = 1>
 static int64_t vox_blocks(const GeoK &G) {
     const int64_t P = (int64_t)((G.nz + 63) / 64) * ((G.nx + 3) / 4);
-    return 8 * ((P + 7) / 8) * G.ny;
+    return 8 * ((P + 7) / 8) * ((G.ny + NP - 1) / NP);
 }
 
 // Sum of `v` over the block (256 threads), written to part[blockIdx.x].
@@ -89,25 +93,49 @@ __device__ __forceinline__ void block_partial(double v, double *part) {
 // ---------------------------------------------------------------- weights
 
 // w1 = (sqrt(|D x|^2) + tau^2)^(-1/2), w2 = (sqrt(|D x - D xp|^2) + tau^2)^(-1/2)
-// (paper Sec. 2.2.1, definition of W~*; Sec. 2.2.2 for the PICCS pair).
-__global__ void __launch_bounds__(256)
-k_weights(GeoK G, const float *__restrict__ x, const float *__restrict__ xp, float tau2,
-          float *__restrict__ w1, float *__restrict__ w2) {
-    const VoxIdx v = vox_index(G);
-    if (!v.ok) return;
-    const int64_t c = v.c;
-    const bool hx_ = v.i < G.nx - 1, hy_ = v.j < G.ny - 1, hz_ = v.k < G.nz - 1;
-    // every read is issued unconditionally (offset 0 at the volume's far faces) and
-    // the face condition selects afterwards, so all reads are in flight at once
-    const int64_t ox = hx_ ? G.Z : 0, oy = hy_ ? (int64_t)G.nx * G.Z : 0, oz = hz_ ? 1 : 0;
-    const float x0 = x[c], p0 = xp[c];
-    const float xx = x[c + ox], xy = x[c + oy], xz = x[c + oz];
-    const float px = xp[c + ox], py = xp[c + oy], pz = xp[c + oz];
+// (paper Sec. 2.2.1, definition of W~*; Sec. 2.2.2 for the PICCS pair), from a
+// cell's values and its forward neighbours along x, y, z; a neighbour past the
+// volume's far face contributes a zero difference.
+__device__ __forceinline__ void tv_weights(float x0, float p0, float xx, float xy, float xz,
+                                           float px, float py, float pz, bool hx_, bool hy_,
+                                           bool hz_, float tau2, float &w1, float &w2) {
     const float gx = hx_ ? x0 - xx : 0.f, gy = hy_ ? x0 - xy : 0.f, gz = hz_ ? x0 - xz : 0.f;
     const float hx = hx_ ? gx - (p0 - px) : 0.f, hy = hy_ ? gy - (p0 - py) : 0.f,
                 hz = hz_ ? gz - (p0 - pz) : 0.f;
-    w1[c] = 1.0f / sqrtf(sqrtf(gx * gx + gy * gy + gz * gz) + tau2);
-    w2[c] = 1.0f / sqrtf(sqrtf(hx * hx + hy * hy + hz * hz) + tau2);
+    w1 = 1.0f / sqrtf(sqrtf(gx * gx + gy * gy + gz * gz) + tau2);
+    w2 = 1.0f / sqrtf(sqrtf(hx * hx + hy * hy + hz * hz) + tau2);
+}
+
+// Two cells per thread, in planes j and j + 1: plane j's y neighbour is plane
+// j + 1's own cell, and each thread keeps twice the reads in flight (with one
+// cell per thread this kernel streams two arrays and has too few bytes in flight
+// to approach the HBM rate).
+__global__ void __launch_bounds__(256)
+k_weights(GeoK G, const float *__restrict__ x, const float *__restrict__ xp, float tau2,
+          float *__restrict__ w1, float *__restrict__ w2) {
+    const VoxIdx v = vox_index<2>(G);
+    if (!v.ok) return;
+    const int64_t sy = (int64_t)G.nx * G.Z;
+    const bool hx_ = v.i < G.nx - 1, hz_ = v.k < G.nz - 1;
+    const bool two = v.j + 1 < G.ny;        // plane j + 1 exists (= plane j has a y neighbour)
+    const bool hy1 = v.j + 2 < G.ny;        // plane j + 1 has a y neighbour
+    // every read is issued unconditionally (offset 0 where a neighbour or the
+    // second plane does not exist) and the face conditions select afterwards
+    const int64_t ox = hx_ ? G.Z : 0, oz = hz_ ? 1 : 0;
+    const int64_t c0 = v.c, c1 = two ? c0 + sy : c0, oy1 = hy1 ? sy : 0;
+    const float x0 = x[c0], p0 = xp[c0], x1 = x[c1], p1 = xp[c1];
+    const float xx0 = x[c0 + ox], xz0 = x[c0 + oz], px0 = xp[c0 + ox], pz0 = xp[c0 + oz];
+    const float xx1 = x[c1 + ox], xz1 = x[c1 + oz], px1 = xp[c1 + ox], pz1 = xp[c1 + oz];
+    const float xy1 = x[c1 + oy1], py1 = xp[c1 + oy1];
+    float a, b;
+    tv_weights(x0, p0, xx0, x1, xz0, px0, p1, pz0, hx_, two, hz_, tau2, a, b);
+    w1[c0] = a;
+    w2[c0] = b;
+    if (two) {
+        tv_weights(x1, p1, xx1, xy1, xz1, px1, py1, pz1, hx_, hy1, hz_, tau2, a, b);
+        w1[c1] = a;
+        w2[c1] = b;
+    }
 }
 
 // ---------------------------------------------------------------- regulariser, forward
@@ -346,6 +374,26 @@ __device__ __forceinline__ double uhat_scale(int dt, double beta, double uref) {
     return exp2(rint(log2(uref / beta)));
 }
 
+// First stage of a norm's reduction when there are many partials: block b sums
+// its contiguous share of p0[0, n0) followed by p1[0, n1), in a fixed order, into
+// out[b].  One 1024-thread block reading hundreds of thousands of partials is
+// bound by its own load latency (about 130 us at 512 x 512 x 400); 256 blocks
+// read them in a few microseconds and k_red then sums 256 values.
+constexpr int kPsumBlocks = 256;
+constexpr int64_t kPsumMin = 16384;  // fewer partials go to k_red directly
+
+__global__ void __launch_bounds__(256)
+k_psum(const double *__restrict__ p0, int64_t n0, const double *__restrict__ p1, int64_t n1,
+       double *out, const int *brk) {
+    if (*brk == 2) return;
+    const int64_t n = n0 + n1;
+    const int64_t per = (n + kPsumBlocks - 1) / kPsumBlocks;
+    const int64_t lo = (int64_t)blockIdx.x * per, hi = lo + per < n ? lo + per : n;
+    double a = 0.0;
+    for (int64_t t = lo + threadIdx.x; t < hi; t += 256) a += t < n0 ? p0[t] : p1[t - n0];
+    block_partial(a, out);
+}
+
 template <int MODE>
 __global__ void __launch_bounds__(1024)
 k_red(const double *__restrict__ p0, int64_t n0, const double *__restrict__ p1, int64_t n1,
@@ -472,6 +520,7 @@ struct Workspace {
     float *bhat, *uhat;
     unsigned short *uhat16;  // 16-bit copy of u-hat read by the adjoint (mixed forms)
     double *pf, *pr, *pa;  // partials: forward, regF, regA
+    double *pp;            // first-stage sums of the partials (k_psum)
     int64_t nf, nr;
     float *Q;              // reorthogonalisation basis: n_inner padded volumes (base P)
     double *pq, *qcoef;    // its dot partials [n_inner][kQBlocks] and coefficients
@@ -523,6 +572,7 @@ static Workspace carve(const cbct_geom *g, const GeoK &G, const piccs_params *p,
     W.pf = (double *)take(sizeof(double) * (size_t)W.nf);
     W.pr = (double *)take(sizeof(double) * (size_t)W.nr);
     W.pa = (double *)take(sizeof(double) * (size_t)W.nr);
+    W.pp = (double *)take(sizeof(double) * (size_t)kPsumBlocks);
     if (p->reorth) {
         W.pq = (double *)take(sizeof(double) * (size_t)kQBlocks * p->n_inner);
         W.qcoef = (double *)take(sizeof(double) * (size_t)p->n_inner);
@@ -617,10 +667,25 @@ void solve_enqueue(cbct_geom *g, const float *b, const float *xp, float *x,
     fa.uin = nullptr;
     fa.partial = W.pf;
     fa.brk = W.fl;
+    // a norm and its LSQR step (k_red), with k_psum first when the partials are many
+    auto red = [&](auto kern, const double *p0, int64_t n0, const double *p1, int64_t n1,
+                   int it) {
+        if (n0 + n1 > kPsumMin) {
+            hipLaunchKernelGGL(k_psum, dim3(kPsumBlocks), dim3(256), 0, s, p0, n0, p1, n1, W.pp,
+                               W.fl);
+            p0 = W.pp;
+            n0 = kPsumBlocks;
+            p1 = nullptr;
+            n1 = 0;
+        }
+        hipLaunchKernelGGL(kern, dim3(1), dim3(1024), 0, s, p0, n0, p1, n1, W.sc, W.fl, W.hist,
+                           it, dt, nvox, uref);
+    };
     int it_global = 0;
     for (int ko = 0; ko < p->n_outer; ++ko) {
         hipLaunchKernelGGL(k_outer_begin, dim3(1), dim3(1), 0, s, W.sc, W.fl);
-        hipLaunchKernelGGL(k_weights, dim3(nvb), dim3(256), 0, s, G, W.x, W.xp, tau2, W.W1,
+        hipLaunchKernelGGL(k_weights, dim3((unsigned)vox_blocks<2>(G)), dim3(256), 0, s, G, W.x,
+                           W.xp, tau2, W.W1,
                            W.W2);
         // beta_1 u_1 = b~ - A~ x_{k-1} (float32 throughout, as the restart's adjoint)
         fa.vol = W.x; fa.uin = W.bhat; fa.s1 = W.sc + SC_M1; fa.s2 = W.sc + SC_P1;
@@ -629,16 +694,13 @@ void solve_enqueue(cbct_geom *g, const float *b, const float *xp, float *x,
         hipLaunchKernelGGL(regF_init, dim3(nvb), dim3(256), 0, s, G, W.x, W.xp, W.W1,
                            W.W2, W.u1, W.u2, W.cstride, alpha, lam, W.sc + SC_M1,
                            W.sc + SC_ZERO, W.pr, W.fl);
-        hipLaunchKernelGGL(k_red<RED_INIT_BETA>, dim3(1), dim3(1024), 0, s, W.pf, W.nf,
-                           W.pr, W.nr, W.sc, W.fl, W.hist, 0, dt, nvox, uref);
+        red(k_red<RED_INIT_BETA>, W.pf, W.nf, W.pr, W.nr, 0);
         // alpha_1 v_1 = A~^T u_1
         launch_back(G, W.uhat, W.t, W.fl, s);
         hipLaunchKernelGGL(regA, dim3(nvb), dim3(256), 0, s, G, W.t, W.W1, W.W2, W.u1,
                            W.u2, W.cstride, alpha, lam, W.V, W.sc + SC_BACK_S1,
                            W.sc + SC_BACK_S2, W.pa, W.fl);
-        hipLaunchKernelGGL(k_red<RED_INIT_ALPHA>, dim3(1), dim3(1024), 0, s, W.pa, W.nr,
-                           (const double *)nullptr, (int64_t)0, W.sc, W.fl, W.hist, 0, dt,
-                           nvox, uref);
+        red(k_red<RED_INIT_ALPHA>, W.pa, W.nr, nullptr, 0, 0);
         xw(basis(0));
         for (int ki = 0; ki < p->n_inner; ++ki, ++it_global) {
             fa.vol = dt == CBCT_F32 ? (const void *)W.V : (const void *)W.V16;
@@ -652,8 +714,7 @@ void solve_enqueue(cbct_geom *g, const float *b, const float *xp, float *x,
             hipLaunchKernelGGL(regF_step, dim3(nvb), dim3(256), 0, s, G, W.V,
                                (const float *)nullptr, W.W1, W.W2, W.u1, W.u2, W.cstride,
                                alpha, lam, W.sc + SC_REG_S1, W.sc + SC_REG_S2, W.pr, W.fl);
-            hipLaunchKernelGGL(k_red<RED_BETA>, dim3(1), dim3(1024), 0, s, W.pf, W.nf,
-                               W.pr, W.nr, W.sc, W.fl, W.hist, it_global, dt, nvox, uref);
+            red(k_red<RED_BETA>, W.pf, W.nf, W.pr, W.nr, it_global);
             if (W.uhat16)
                 launch_back(G, W.uhat16, W.t, W.fl, s, dt, W.sc + SC_U16_SCALE);
             else
@@ -662,10 +723,8 @@ void solve_enqueue(cbct_geom *g, const float *b, const float *xp, float *x,
                                W.u2, W.cstride, alpha, lam, W.V, W.sc + SC_BACK_S1,
                                W.sc + SC_BACK_S2, W.pa, W.fl);
             if (reorth) cgs2(ki + 1);
-            hipLaunchKernelGGL(k_red<RED_ALPHA>, dim3(1), dim3(1024), 0, s,
-                               reorth ? W.pq : W.pa, reorth ? (int64_t)kQBlocks : W.nr,
-                               (const double *)nullptr, (int64_t)0, W.sc, W.fl, W.hist,
-                               it_global, dt, nvox, uref);
+            red(k_red<RED_ALPHA>, reorth ? W.pq : W.pa, reorth ? (int64_t)kQBlocks : W.nr,
+                nullptr, 0, it_global);
             xw(basis(ki + 1));
         }
     }
@@ -728,7 +787,7 @@ int piccs_weights(const cbct_geom *gc, const float *x, const float *xp, double t
                   *B = tmp + 3 * pf + kGuard;
             vol_to_cols(G, x, X, s);
             vol_to_cols(G, xp, XP, s);
-            hipLaunchKernelGGL(k_weights, dim3((unsigned)vox_blocks(G)), dim3(256), 0, s, G, X,
+            hipLaunchKernelGGL(k_weights, dim3((unsigned)vox_blocks<2>(G)), dim3(256), 0, s, G, X,
                                XP, (float)(tau * tau), A, B);
             CBCT_HIP(hipGetLastError());
             cols_to_vol(G, A, w1, s);

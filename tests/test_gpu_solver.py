@@ -59,6 +59,22 @@ def test_weights_parity(orc, lib):
     assert rel(host(w2), w2o) <= 1e-5
 
 
+@pytest.mark.parametrize("ny", [1, 2, 7, 8])
+def test_weights_parity_plane_pairs(orc, lib, ny):
+    """The weights kernel takes two y-planes per thread: odd and even plane counts
+    (a lone last plane, a single plane), ragged x and z, against the oracle."""
+    rng = np.random.default_rng(30 + ny)
+    d = dict(nx=13, ny=ny, nz=70, vx=1.0, vy=1.0, vz=1.0, nu=8, nv=8, du=1.0, dv=1.0,
+             dso=60.0, dsd=100.0, n_views=2)
+    gg = lib.Geometry.from_dict(d)
+    x = rng.uniform(size=gg.vol_shape).astype(np.float32).astype(np.float64)
+    xp = (x + 0.2 * rng.uniform(size=gg.vol_shape)).astype(np.float32).astype(np.float64)
+    w1o, w2o = orc.weights(x, xp, 0.1)
+    w1, w2 = lib.weights(gg, dev(x), dev(xp), 0.1)
+    assert rel(host(w1), w1o) <= 1e-5
+    assert rel(host(w2), w2o) <= 1e-5
+
+
 def _gpu_solve(lib, d, b, xp, x0, p):
     gg = lib.Geometry.from_dict(d)
     x = dev(x0)
@@ -252,6 +268,27 @@ def test_solve_with_adjoint_view_chunks_same_bits(lib, prec):
         assert rep["inner_done"] == 6
         outs.append(x)
     assert torch.equal(outs[0], outs[1])
+
+
+def test_many_partials_against_oracle(orc, lib):
+    """A volume whose stencil partials (20 480) take the two-stage reduction
+    (k_psum, then k_red), as the benchmark sizes do: FP32 and mixed BF16 solves
+    against the FP64 oracle."""
+    rng = np.random.default_rng(29)
+    d = dict(nx=128, ny=128, nz=320, vx=1.0, vy=1.0, vz=1.0, nu=128, nv=300, du=1.6, dv=1.6,
+             dso=300.0, dsd=500.0, n_views=12)
+    og = orc.Geometry.from_dict(d)
+    xp = rng.uniform(size=og.vol_shape).astype(np.float32).astype(np.float64)
+    xt = xp + 0.3 * (rng.uniform(size=og.vol_shape) > 0.95)
+    b = orc.forward(og, xt).astype(np.float32).astype(np.float64)
+    ref = orc.irn_piccs(og, b, xp, xp, 0.5, 1.5, 0.2, 2, 3)
+    xg, rep = _gpu_solve(lib, d, b, xp, xp, lib.SolveParams(0.5, 1.5, 0.2, 2, 3))
+    assert rep["inner_done"] == 6 and rep["breakdown"] == 0
+    assert rel(xg, ref.x) <= SOLVE_TOL
+    np.testing.assert_allclose(rep["phibar"], ref.phibar, rtol=SOLVE_TOL)
+    xm, _ = _gpu_solve(lib, d, b, xp, xp,
+                       lib.SolveParams(0.5, 1.5, 0.2, 2, 3, precision=lib.PREC_MIXED_BF16))
+    assert rel(xm, ref.x) <= 1e-3
 
 
 def test_mixed_forms_on_ragged_geometry(orc, lib):
