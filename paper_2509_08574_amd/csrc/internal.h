@@ -161,7 +161,7 @@ struct FwdArgs {
     const int *brk;          // FWD_SOLVER: breakdown flag (2 = stopped)
     unsigned long long *count;  // FWD_COUNT
     float scale;             // FWD_PLAIN: output multiplier (value of one stored unit)
-    // FWD_SOLVER, mixed forms: 16-bit copy of the new u-hat for the adjoint
+    // FWD_SOLVER, *_ADJ16 forms: 16-bit copy of the new u-hat for the adjoint
     // (bf16, or fp16 holding u-hat * *u16_scale, a power of two), or null
     void *u16;
     int u16_dt;              // CBCT_BF16 or CBCT_F16

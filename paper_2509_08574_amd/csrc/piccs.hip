@@ -30,7 +30,7 @@ enum Sc {
     SC_M1, SC_P1, SC_ZERO,
     SC_INNER_DONE, SC_OUTER_DONE, SC_NBRK,
     SC_V16_SCALE,  // power-of-two scale of the 16-bit shadow of V (mixed forms)
-    SC_U16_SCALE,  // power-of-two scale of the 16-bit copy of u-hat (mixed fp16 form)
+    SC_U16_SCALE,  // power-of-two scale of the 16-bit copy of u-hat (fp16 ADJ16 form)
     SC_NUMERIC,    // 1 once a norm came out non-finite (the solve stopped there)
     SC_COUNT = 32
 };
@@ -518,7 +518,7 @@ struct Workspace {
     size_t v16_bytes;
     int64_t cstride;                                // floats between components
     float *bhat, *uhat;
-    unsigned short *uhat16;  // 16-bit copy of u-hat read by the adjoint (mixed forms)
+    unsigned short *uhat16;  // 16-bit copy of u-hat read by the adjoint (*_ADJ16 forms)
     double *pf, *pr, *pa;  // partials: forward, regF, regA
     double *pp;            // first-stage sums of the partials (k_psum)
     int64_t nf, nr;
@@ -705,7 +705,7 @@ void solve_enqueue(cbct_geom *g, const float *b, const float *xp, float *x,
         for (int ki = 0; ki < p->n_inner; ++ki, ++it_global) {
             fa.vol = dt == CBCT_F32 ? (const void *)W.V : (const void *)W.V16;
             fa.uin = W.uhat; fa.s1 = W.sc + SC_FWD_S1; fa.s2 = W.sc + SC_FWD_S2;
-            // mixed forms: the inner forward also writes the adjoint's 16-bit input
+            // *_ADJ16 forms: the inner forward also writes the adjoint's 16-bit input
             fa.u16 = W.uhat16; fa.u16_dt = dt; fa.u16_scale = W.sc + SC_U16_SCALE;  // or null
             launch_forward(G, FWD_SOLVER, fa, s,
                            dt == CBCT_BF16  ? CBCT_BF16_PAIR

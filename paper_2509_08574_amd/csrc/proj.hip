@@ -407,7 +407,7 @@ k_fwd(GeoK G, FwdArgs a) {
             if (ok) {
                 a.out[o] = un;
                 sq += (double)un * (double)un / (double)L2;  // |u|^2 = u-hat^2 / L^2
-                // the adjoint's 16-bit input (mixed forms): the same value rounded
+                // the adjoint's 16-bit input (*_ADJ16 forms): the same value rounded
                 if (a.u16) {
                     unsigned short h;
                     if (a.u16_dt == CBCT_BF16)

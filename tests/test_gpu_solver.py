@@ -217,10 +217,10 @@ def test_mixed_precision_solve_within_1e3_of_fp64(orc, lib, prec):
     assert rep["inner_done"] == sp["n_outer"] * sp["n_inner"]
 
 
-# A small volume seen on a tall detector: a 16 x 16 column tile's per-view
-# detector footprint in float32, (16 h sqrt(2) DSD / (DSO du) + 2) x nv x 4 B =
-# 36 x 1024 x 4 B = 147 KB, is past the 128 KB above which the mixed forms' adjoint
-# reads the 16-bit copy of u-hat (at 256^3 it is 91 KB, at 512x512x400 193 KB).
+# A small volume seen on a tall detector (1024 rows of 0.25 mm), the shape on
+# which the adjoint's 16-bit input pays most: a 16 x 16 column tile's per-view
+# detector footprint in float32, (16 h sqrt(2) DSD / (DSO du) + 2) x nv x 4 B, is
+# 36 x 1024 x 4 B = 147 KB (at 256^3 it is 91 KB, at 512x512x400 193 KB).
 TALL = dict(nx=20, ny=20, nz=40, vx=1.0, vy=1.0, vz=0.5, nu=24, nv=1024, du=1.0, dv=0.25,
             dso=400.0, dsd=600.0, n_views=9)
 
