@@ -828,8 +828,9 @@ def main():
     ap.add_argument("--serve-budget-gib", type=int, default=64)
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
-              "(multi-GPU view sharding is a design note only)", file=sys.stderr)
+        print(f"bench.py: the projectors and solver run on one GPU; --gpus {args.gpus} is not "
+              "supported (view sharding over several GPUs is described, not built)",
+              file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
