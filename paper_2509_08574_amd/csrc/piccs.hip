@@ -12,6 +12,7 @@
 // Data-space vector: u_b (projections, stored as u-hat = L * u_b in column
 // layout, L = ray length), u1 and u2 (three difference components each, in
 // padded column volumes).  Model-space vectors: padded column volumes.
+#include <rocprofiler-sdk-roctx/roctx.h>
 #include <hip/hip_bf16.h>
 #include <hip/hip_fp16.h>
 
@@ -681,8 +682,11 @@ void solve_enqueue(cbct_geom *g, const float *b, const float *xp, float *x,
         hipLaunchKernelGGL(kern, dim3(1), dim3(1024), 0, s, p0, n0, p1, n1, W.sc, W.fl, W.hist,
                            it, dt, nvox, uref);
     };
+    // marker ranges (rocprofv3 --marker-trace) around each outer step and each
+    // LSQR iteration; they span the host's enqueueing, the kernels run later on s
     int it_global = 0;
     for (int ko = 0; ko < p->n_outer; ++ko) {
+        roctxRangePushA("IRN outer step");
         hipLaunchKernelGGL(k_outer_begin, dim3(1), dim3(1), 0, s, W.sc, W.fl);
         hipLaunchKernelGGL(k_weights, dim3((unsigned)vox_blocks<2>(G)), dim3(256), 0, s, G, W.x,
                            W.xp, tau2, W.W1,
@@ -703,6 +707,7 @@ void solve_enqueue(cbct_geom *g, const float *b, const float *xp, float *x,
         red(k_red<RED_INIT_ALPHA>, W.pa, W.nr, nullptr, 0, 0);
         xw(basis(0));
         for (int ki = 0; ki < p->n_inner; ++ki, ++it_global) {
+            roctxRangePushA("LSQR iteration");
             fa.vol = dt == CBCT_F32 ? (const void *)W.V : (const void *)W.V16;
             fa.uin = W.uhat; fa.s1 = W.sc + SC_FWD_S1; fa.s2 = W.sc + SC_FWD_S2;
             // *_ADJ16 forms: the inner forward also writes the adjoint's 16-bit input
@@ -726,7 +731,9 @@ void solve_enqueue(cbct_geom *g, const float *b, const float *xp, float *x,
             red(k_red<RED_ALPHA>, reorth ? W.pq : W.pa, reorth ? (int64_t)kQBlocks : W.nr,
                 nullptr, 0, it_global);
             xw(basis(ki + 1));
+            roctxRangePop();
         }
+        roctxRangePop();
     }
     hipLaunchKernelGGL(k_solve_end, dim3(1), dim3(1), 0, s, W.sc, W.fl);
     CBCT_HIP(hipGetLastError());

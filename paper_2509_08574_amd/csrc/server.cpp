@@ -8,6 +8,9 @@
 // them.  Every device byte the server uses lives in one arena allocated at
 // create time (the HBM budget), so steady-state serving performs no device
 // allocation and no implicit device synchronisation.
+#include <rocprofiler-sdk-roctx/roctx.h>
+
+#include <cstdio>
 #include <chrono>
 #include <condition_variable>
 #include <cstring>
@@ -81,6 +84,7 @@ struct Payload {
     Pinned b, x, r;          // b copy; result x; scalars + residual history
     hipEvent_t ev = nullptr;
     piccs_report report{};
+    roctx_range_id_t range = 0;  // marker range from launch to collection (0: none)
 };
 
 struct Resident {
@@ -212,6 +216,12 @@ struct cbct_server {
                 CBCT_HIP(hipMemcpyAsync(P.x.p, x_d, sizeof(float) * (size_t)P.n_vox,
                                         hipMemcpyDeviceToHost, s));
                 CBCT_HIP(hipEventRecord(P.ev, s));
+                // a marker range per request, from its launch on a slot to its
+                // collection (seen by rocprofv3 --marker-trace)
+                char name[96];
+                std::snprintf(name, sizeof name, "request %llu patient %d slot %d",
+                              (unsigned long long)j.ticket, (int)j.patient, j.slot);
+                P.range = roctxRangeStartA(name);
             } catch (...) {
                 // order completion after whatever was enqueued
                 if (hipEventRecord(P.ev, s) != hipSuccess) {
@@ -235,6 +245,8 @@ struct cbct_server {
         }
         void collect(Job<Payload> &j) {
             Payload &P = j.payload;
+            if (P.range) roctxRangeStop(P.range);
+            P.range = 0;
             if (j.status == CBCT_PENDING) {
                 report_from_scalars((const double *)P.r.p, &P.report);
                 j.status = CBCT_OK;
