@@ -744,7 +744,11 @@ static int back_views_per_launch(const GeoK &G, size_t sample_bytes) {
     const double cols = 16.0 * h * std::sqrt(2.0) * mag / G.du + 2.0;
     const double rows = std::min((double)G.nv, G.nz * (double)G.hz * mag / G.dv);
     const double per_view = cols * rows * (double)sample_bytes;
-    const int v = std::max(8, (int)(3.5e6 / per_view));
+    // in double until it is known to fit: a footprint far below a byte per view
+    // (a degenerate voxel height) would overflow an int
+    const double vd = per_view > 0.0 ? std::floor(3.5e6 / per_view) : (double)G.nviews;
+    if (vd >= (double)G.nviews) return G.nviews;
+    const int v = std::max(8, (int)vd);
     if (v >= G.nviews) return G.nviews;
     const int chunks = (G.nviews + v - 1) / v;
     return (G.nviews + chunks - 1) / chunks;  // equal chunks
