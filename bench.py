@@ -470,6 +470,73 @@ def cpu_baseline_and_oracle_errors(args, cbct, synth, np, torch, dev, c5):
     return cpu, errs
 
 
+def oracle_c2_solve(args, cbct, synth, np, torch, dev):
+    """The whole 256^3 / 90-view / 512^2 workload on both sides: the FP64 oracle's
+    IRN-PICCS 5 x 10 (55 products of A and A^T, all host threads) timed on this
+    host, and each GPU precision form's final x and phi-bar history against it.
+    Inputs as in the 256^3 case of the default run (prior from the 720-view plain
+    LSQR reconstruction on the GPU), float32-rounded on both sides."""
+    from oracle import oracle as orc
+    gd = synth.geometry("c2")
+    sp = synth.SOLVE_PARAMS["c2"]
+    base, cur = synth.c2_case(sp["seed"])
+    base_d = torch.from_numpy(base.astype(np.float32)).to(dev)
+    gp = cbct.Geometry.from_dict(synth.geometry("c2_prior"))
+    bp = cbct.forward(gp, base_d)
+    xprior = torch.zeros_like(base_d)
+    cbct.solve(gp, bp, xprior, xprior, cbct.SolveParams(0.0, 0.0, sp["tau"], 1, 30), report=False)
+    del bp
+    gp.close()
+    g = cbct.Geometry.from_dict(gd)
+    y = cbct.forward(g, torch.from_numpy(cur.astype(np.float32)).to(dev))
+    b = synth.noisy_line_integrals(y.cpu().numpy(), sp["I0"], seed=sp["seed"] + 100)
+    b = b.astype(np.float32).astype(np.float64)
+    prior = xprior.cpu().numpy().astype(np.float64)
+    del y
+    out = {"workload": "256x256x256 volume at 1 mm, 90 views, 512x512 detector at 0.8 mm, "
+                       "IRN-PICCS 5x10 (55 products), prior from a 720-view plain LSQR "
+                       "reconstruction"}
+    b_d = torch.from_numpy(b.astype(np.float32)).to(dev)
+    xs = {}
+    for name, pr in (("fp32", cbct.PREC_FP32), ("mixed_bf16", cbct.PREC_MIXED_BF16),
+                     ("mixed_f16", cbct.PREC_MIXED_F16)):
+        x = xprior.clone()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        x, rep = cbct.solve(g, b_d, xprior, x, cbct.SolveParams(
+            sp["alpha"], sp["lam"], sp["tau"], sp["n_outer"], sp["n_inner"], precision=pr))
+        xs[name] = (x.cpu().numpy().astype(np.float64), rep["phibar"],
+                    time.perf_counter() - t)
+    g.close()
+    og = orc.Geometry.from_dict(gd)
+    nthreads = orc.num_threads()
+    n_ops = [0]
+    t0 = time.perf_counter()
+
+    def progress(fn, what):
+        def op(v):
+            n_ops[0] += 1
+            log(f"[oracle-c2] {what} {n_ops[0]} of {2 * 55} ({time.perf_counter() - t0:.0f}s)")
+            return fn(og, v)
+        return op
+    ref = orc.irn_piccs(og, b, prior, prior, sp["alpha"], sp["lam"], sp["tau"], sp["n_outer"],
+                        sp["n_inner"], A=progress(orc.forward, "A"),
+                        AT=progress(orc.back, "A^T"))
+    t_or = time.perf_counter() - t0
+    log(f"[oracle-c2] FP64 IRN-PICCS 5x10 at 256^3: {t_or:.0f}s on {nthreads} threads")
+    out["oracle"] = {"s_per_recon": round(t_or, 1), "threads": nthreads,
+                     "cpu_model": cpu_model(), "products": n_ops[0] // 2}
+    for name, (xg, ph, sec) in xs.items():
+        err = float(np.linalg.norm(xg - ref.x) / np.linalg.norm(ref.x))
+        ph_err = float(np.max(np.abs(np.asarray(ph) - np.asarray(ref.phibar))
+                              / np.abs(np.asarray(ref.phibar))))
+        out[name] = {"rel_l2_vs_fp64_oracle": err, "phibar_max_rel_err": ph_err,
+                     "gpu_s_with_report": round(sec, 4),
+                     "oracle_over_gpu": round(t_or / sec, 1)}
+        log(f"[oracle-c2] {name}: rel L2 vs FP64 oracle {err:.3e}, phi-bar {ph_err:.3e}")
+    return out
+
+
 def serving_bench(args, cbct, synth, np, torch, dev):
     """Serving stream: 8 patients with resident priors (volumes 128/256/384^3,
     detector 2n x 2n, 30..120 views per request, needle moved 2..5 voxels),
@@ -804,6 +871,9 @@ def main():
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also run one plain device copy of this many MiB (profiler calibration)")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving stream")
+    ap.add_argument("--oracle-c2-solve", action="store_true",
+                    help="the whole 256^3 IRN-PICCS solve on the FP64 oracle (about 20 min on "
+                         "16 host threads) against every GPU precision form")
     ap.add_argument("--quality", action="store_true",
                     help="only the head / thorax stand-in quality table (PSNR, SSIM)")
     ap.add_argument("--quality-head-only", action="store_true")
@@ -883,6 +953,10 @@ def main():
     if args.quality:
         print(json.dumps({"quality": quality_bench(args, cbct, synth, np, torch, dev)}),
               flush=True)
+        return
+    if args.oracle_c2_solve:
+        print(json.dumps({"oracle_c2_solve": oracle_c2_solve(args, cbct, synth, np, torch,
+                                                             dev)}), flush=True)
         return
 
     c5 = repeated_scans(args, cbct, synth, np, torch, dev, stream)
