@@ -173,6 +173,26 @@ def roofline(dom, nnz, workload):
     return r
 
 
+def stream_copy_gbps(torch, dev):
+    """A plain device copy of 1 GiB (torch's copy kernel), timed with HIP events:
+    the HBM rate a streaming kernel reaches in practice, beside the 8 TB/s of the
+    data sheet."""
+    n = (1 << 30) // 4
+    a = torch.ones(n, dtype=torch.float32, device=dev)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    reps = 5
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    e1.synchronize()
+    return 2.0 * 4.0 * n * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+
+
 def noisy_b(torch, synth, y, I0, seed, dev):
     """Poisson counts at I0 exp(-mu p), clamped >= 1, back to line integrals
     (seeded, on the device)."""
@@ -255,6 +275,23 @@ def repeated_scans(args, cbct, synth, np, torch, dev, stream):
                        "rel_err_prior_vs_truth": round(err_prior, 5),
                        "improves_on_prior": err < err_prior,
                        "needle_change_err": round(chg, 4)}
+        # later scans of the same chain with b arriving in page-locked host memory
+        # and x returned there: H2D of b, the solve, D2H of x; median of three
+        b_host = torch.empty(bs[0].shape, dtype=torch.float32, pin_memory=True)
+        x_host = torch.empty(x.shape, dtype=torch.float32, pin_memory=True)
+        b_dev = torch.empty_like(bs[0])
+        with_copies = []
+        for r in range(3):
+            b_host.copy_(bs[(args.warmup + args.steps + r) % 10])
+            torch.cuda.synchronize()
+            ts = time.perf_counter()
+            b_dev.copy_(b_host, non_blocking=True)
+            cbct.solve(g, b_dev, xp, x, p, workspace=ws, report=False)
+            x_host.copy_(x, non_blocking=True)
+            torch.cuda.synchronize()
+            with_copies.append(time.perf_counter() - ts)
+        forms[name]["s_per_recon_with_copies"] = round(float(np.median(with_copies)), 4)
+        del b_host, x_host, b_dev
         xs[name] = x
         log(f"[bench] 512x512x400 {name}: {args.steps} steps, {1e3 * total / args.steps:.1f} "
             f"ms/recon; scan {last + 1}: rel err vs truth {err:.4f} (prior {err_prior:.4f}), "
@@ -959,7 +996,13 @@ def main():
                                                              dev)}), flush=True)
         return
 
+    copy_gbps = stream_copy_gbps(torch, dev)
+    log(f"[bench] device copy of 1 GiB: {copy_gbps:.0f} GB/s")
     c5 = repeated_scans(args, cbct, synth, np, torch, dev, stream)
+    for part in (c5["roofline"].get("hbm"),):
+        if part:
+            part["stream_copy_GBps"] = round(copy_gbps, 1)
+            part["frac_of_stream_copy"] = round(part["achieved"] / copy_gbps, 4)
     f32 = c5["forms"]["fp32"]
     c2 = None if args.no_c2 else c2_case_forms(args, cbct, synth, np, torch, dev, stream)
     c3 = None if args.no_c3 else c3_precision_bench(args, cbct, synth, np, torch, dev)
