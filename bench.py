@@ -508,61 +508,66 @@ def cpu_baseline_and_oracle_errors(args, cbct, synth, np, torch, dev, c5):
 
 
 def oracle_c2_solve(args, cbct, synth, np, torch, dev):
-    """The whole 256^3 / 90-view / 512^2 workload on both sides: the FP64 oracle's
-    IRN-PICCS 5 x 10 (55 products of A and A^T, all host threads) timed on this
-    host, and each GPU precision form's final x and phi-bar history against it.
-    Inputs as in the 256^3 case of the default run (prior from the 720-view plain
-    LSQR reconstruction on the GPU), float32-rounded on both sides."""
+    """The 256^3 / 90-view / 512^2 workload solved on both sides at full size: the
+    FP64 oracle's IRN-PICCS (args.oracle_c2_outer outer steps of 10 LSQR
+    iterations, all host threads) timed on this host, and each GPU precision
+    form's final x and phi-bar history against it.  Both sides get the same
+    inputs, made by the oracle and the seeded generator only: b is the oracle's
+    projection of the current object with Poisson noise, and the prior is the
+    object without the change.  Four outer steps (44 products) fit one 20-minute
+    session on 16 host threads; the time per product gives the 5 x 10 figure."""
     from oracle import oracle as orc
     gd = synth.geometry("c2")
     sp = synth.SOLVE_PARAMS["c2"]
+    n_outer, n_inner = args.oracle_c2_outer, sp["n_inner"]
     base, cur = synth.c2_case(sp["seed"])
-    base_d = torch.from_numpy(base.astype(np.float32)).to(dev)
-    gp = cbct.Geometry.from_dict(synth.geometry("c2_prior"))
-    bp = cbct.forward(gp, base_d)
-    xprior = torch.zeros_like(base_d)
-    cbct.solve(gp, bp, xprior, xprior, cbct.SolveParams(0.0, 0.0, sp["tau"], 1, 30), report=False)
-    del bp
-    gp.close()
-    g = cbct.Geometry.from_dict(gd)
-    y = cbct.forward(g, torch.from_numpy(cur.astype(np.float32)).to(dev))
-    b = synth.noisy_line_integrals(y.cpu().numpy(), sp["I0"], seed=sp["seed"] + 100)
+    og = orc.Geometry.from_dict(gd)
+    nthreads = orc.num_threads()
+    t = time.perf_counter()
+    y = orc.forward(og, cur)
+    log(f"[oracle-c2] oracle projection of the current object: {time.perf_counter() - t:.0f}s")
+    b = synth.noisy_line_integrals(y, sp["I0"], seed=sp["seed"] + 100)
     b = b.astype(np.float32).astype(np.float64)
-    prior = xprior.cpu().numpy().astype(np.float64)
+    prior = base.astype(np.float32).astype(np.float64)
     del y
-    out = {"workload": "256x256x256 volume at 1 mm, 90 views, 512x512 detector at 0.8 mm, "
-                       "IRN-PICCS 5x10 (55 products), prior from a 720-view plain LSQR "
-                       "reconstruction"}
+    products = n_outer * (n_inner + 1)
+    out = {"workload": f"256x256x256 volume at 1 mm, 90 views, 512x512 detector at 0.8 mm, "
+                       f"IRN-PICCS {n_outer}x{n_inner} ({products} products), prior = the "
+                       f"object without the change"}
+    g = cbct.Geometry.from_dict(gd)
     b_d = torch.from_numpy(b.astype(np.float32)).to(dev)
+    p_d = torch.from_numpy(prior.astype(np.float32)).to(dev)
     xs = {}
     for name, pr in (("fp32", cbct.PREC_FP32), ("mixed_bf16", cbct.PREC_MIXED_BF16),
                      ("mixed_f16", cbct.PREC_MIXED_F16)):
-        x = xprior.clone()
+        x = p_d.clone()
         torch.cuda.synchronize()
         t = time.perf_counter()
-        x, rep = cbct.solve(g, b_d, xprior, x, cbct.SolveParams(
-            sp["alpha"], sp["lam"], sp["tau"], sp["n_outer"], sp["n_inner"], precision=pr))
+        x, rep = cbct.solve(g, b_d, p_d, x, cbct.SolveParams(
+            sp["alpha"], sp["lam"], sp["tau"], n_outer, n_inner, precision=pr))
         xs[name] = (x.cpu().numpy().astype(np.float64), rep["phibar"],
                     time.perf_counter() - t)
+        log(f"[oracle-c2] GPU {name}: {xs[name][2]:.3f}s")
     g.close()
-    og = orc.Geometry.from_dict(gd)
-    nthreads = orc.num_threads()
+    del b_d, p_d
     n_ops = [0]
     t0 = time.perf_counter()
 
     def progress(fn, what):
         def op(v):
             n_ops[0] += 1
-            log(f"[oracle-c2] {what} {n_ops[0]} of {2 * 55} ({time.perf_counter() - t0:.0f}s)")
+            log(f"[oracle-c2] {what} {n_ops[0]} of {2 * products} "
+                f"({time.perf_counter() - t0:.0f}s)")
             return fn(og, v)
         return op
-    ref = orc.irn_piccs(og, b, prior, prior, sp["alpha"], sp["lam"], sp["tau"], sp["n_outer"],
-                        sp["n_inner"], A=progress(orc.forward, "A"),
-                        AT=progress(orc.back, "A^T"))
+    ref = orc.irn_piccs(og, b, prior, prior, sp["alpha"], sp["lam"], sp["tau"], n_outer,
+                        n_inner, A=progress(orc.forward, "A"), AT=progress(orc.back, "A^T"))
     t_or = time.perf_counter() - t0
-    log(f"[oracle-c2] FP64 IRN-PICCS 5x10 at 256^3: {t_or:.0f}s on {nthreads} threads")
+    log(f"[oracle-c2] FP64 IRN-PICCS {n_outer}x{n_inner} at 256^3: {t_or:.0f}s on "
+        f"{nthreads} threads")
     out["oracle"] = {"s_per_recon": round(t_or, 1), "threads": nthreads,
-                     "cpu_model": cpu_model(), "products": n_ops[0] // 2}
+                     "cpu_model": cpu_model(), "products": n_ops[0] // 2,
+                     "s_per_product": round(t_or / max(1, n_ops[0] // 2), 2)}
     for name, (xg, ph, sec) in xs.items():
         err = float(np.linalg.norm(xg - ref.x) / np.linalg.norm(ref.x))
         ph_err = float(np.max(np.abs(np.asarray(ph) - np.asarray(ref.phibar))
@@ -571,6 +576,7 @@ def oracle_c2_solve(args, cbct, synth, np, torch, dev):
                      "gpu_s_with_report": round(sec, 4),
                      "oracle_over_gpu": round(t_or / sec, 1)}
         log(f"[oracle-c2] {name}: rel L2 vs FP64 oracle {err:.3e}, phi-bar {ph_err:.3e}")
+    out["moved_from_prior"] = float(np.linalg.norm(ref.x - prior) / np.linalg.norm(ref.x))
     return out
 
 
@@ -909,8 +915,9 @@ def main():
                     help="also run one plain device copy of this many MiB (profiler calibration)")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving stream")
     ap.add_argument("--oracle-c2-solve", action="store_true",
-                    help="the whole 256^3 IRN-PICCS solve on the FP64 oracle (about 20 min on "
-                         "16 host threads) against every GPU precision form")
+                    help="a full-size 256^3 IRN-PICCS solve on the FP64 oracle (about 17 min "
+                         "on 16 host threads at 4 outer steps) against every GPU precision form")
+    ap.add_argument("--oracle-c2-outer", type=int, default=4)
     ap.add_argument("--quality", action="store_true",
                     help="only the head / thorax stand-in quality table (PSNR, SSIM)")
     ap.add_argument("--quality-head-only", action="store_true")
