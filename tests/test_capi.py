@@ -77,6 +77,35 @@ def test_workspace_bytes_and_param_checks(lib):
             lib.workspace_bytes(g, bad)
 
 
+def test_precision_forms_and_their_workspace(lib):
+    """The five precision forms are accepted; the *_ADJ16 forms add the 16-bit copy
+    of u-hat (2 bytes per projection sample, 8 bytes of padding) to the mixed
+    forms' workspace; an unknown form is rejected."""
+    g = lib.Geometry(**C1)
+    ws = {pr: lib.workspace_bytes(g, lib.SolveParams(1.0, 2.0, 0.1, 3, 5, precision=pr))
+          for pr in (lib.PREC_FP32, lib.PREC_MIXED_BF16, lib.PREC_MIXED_F16,
+                     lib.PREC_MIXED_BF16_ADJ16, lib.PREC_MIXED_F16_ADJ16)}
+    assert ws[lib.PREC_MIXED_BF16] == ws[lib.PREC_MIXED_F16] > ws[lib.PREC_FP32]
+    assert ws[lib.PREC_MIXED_BF16_ADJ16] == ws[lib.PREC_MIXED_F16_ADJ16]
+    extra = ws[lib.PREC_MIXED_BF16_ADJ16] - ws[lib.PREC_MIXED_BF16]
+    assert 2 * 48 * 96 * 96 + 8 <= extra <= 2 * 48 * 96 * 96 + 8 + 256
+    for bad in (-1, 5):
+        with pytest.raises(lib.CbctError):
+            lib.workspace_bytes(g, lib.SolveParams(1.0, 2.0, 0.1, 3, 5, precision=bad))
+
+
+def test_back_views_knob_is_validated(lib):
+    g = lib.Geometry(**C1)
+    for v in (0, 1, 7, 48, 1000):
+        g.set_back_views(v)
+    with pytest.raises(lib.CbctError) as ei:
+        g.set_back_views(-1)
+    assert ei.value.code == lib.ERR_INVALID
+    so = ctypes.CDLL(lib.LIB_PATH)
+    so.cbct_geom_set_back_views.argtypes = [ctypes.c_void_p, ctypes.c_int]
+    assert so.cbct_geom_set_back_views(None, 4) == lib.ERR_INVALID
+
+
 def test_null_arguments_are_rejected(lib):
     g = lib.Geometry(**C1)
     so = lib._lib
