@@ -6,8 +6,9 @@
 //   A~ = [A; alpha W1 D; lambda W2 D],   b~ = [b; 0; lambda W2 D x_p].
 // LSQR (Paige & Saunders 1982) keeps u (data space) and v (model space)
 // unnormalised in storage: U = beta * u, V = alpha * v.  Every kernel reads its
-// scale factors from a float64 scalar block that the single-block reduction
-// kernels update, so the host enqueues the whole solve without waiting.
+// scale factors from a float64 scalar block that the reduction kernels update
+// (k_psum's first stage over many blocks, then k_red's single block, which also
+// runs LSQR's scalar step), so the host enqueues the whole solve without waiting.
 //
 // Data-space vector: u_b (projections, stored as u-hat = L * u_b in column
 // layout, L = ray length), u1 and u2 (three difference components each, in
