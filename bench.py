@@ -507,11 +507,12 @@ def cpu_baseline_and_oracle_errors(args, cbct, synth, np, torch, dev, c5):
     return cpu, errs
 
 
-def oracle_c2_solve(args, cbct, synth, np, torch, dev):
-    """The 256^3 / 90-view / 512^2 workload solved on both sides at full size: the
-    FP64 oracle's IRN-PICCS (args.oracle_c2_outer outer steps of 10 LSQR
-    iterations, all host threads) timed on this host, and each GPU precision
-    form's final x and phi-bar history against it.  Both sides get the same
+def cpu_baseline_c2_solve(args, cbct, synth, np, torch, dev):
+    """The cpu_baseline leg at full size (--oracle-c2-solve): the 256^3 / 90-view /
+    512^2 workload solved on both sides, the FP64 oracle's IRN-PICCS
+    (args.oracle_c2_outer outer steps of 10 LSQR iterations, all host threads)
+    timed on this host, and each GPU precision form's final x and phi-bar
+    history compared with the oracle's.  Both sides get the same
     inputs, made by the oracle and the seeded generator only: b is the oracle's
     projection of the current object with Poisson noise, and the prior is the
     object without the change.  Four outer steps (44 products) fit one 20-minute
@@ -999,8 +1000,8 @@ def main():
               flush=True)
         return
     if args.oracle_c2_solve:
-        print(json.dumps({"oracle_c2_solve": oracle_c2_solve(args, cbct, synth, np, torch,
-                                                             dev)}), flush=True)
+        print(json.dumps({"oracle_c2_solve": cpu_baseline_c2_solve(args, cbct, synth, np,
+                                                                   torch, dev)}), flush=True)
         return
 
     copy_gbps = stream_copy_gbps(torch, dev)
