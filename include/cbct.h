@@ -121,7 +121,7 @@ int cbct_back(const cbct_geom *g, const void *y, cbct_dtype yt, float y_scale, f
  * chunk of consecutive views; each launch continues the cells' float32 partial
  * sums left in the output by the one before.  Short chunks keep the detector
  * data that the blocks resident on one XCD read within that XCD's L2; the
- * automatic choice bounds one 16 x 16-column tile's detector footprint over a
+ * automatic choice bounds a 16 x 16-column square's detector footprint over a
  * chunk at about 3.5 MB.  Every chunk size gives the same results bit for bit.
  * Takes effect on the next call with g; not to be called while another thread
  * uses g.  Errors: CBCT_ERR_INVALID (null g, views < 0).

@@ -90,7 +90,8 @@ k_fdk_back(GeoK G, const float *__restrict__ q, float *__restrict__ out, int ksp
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int nzs = (G.nz + kspan - 1) / kspan;
     const int64_t lw = (int64_t)xcd_remap(blockIdx.x, gridDim.x) * 4 + w;
-    // 16 x 16 tiles of columns, as in the adjoint projector
+    // 16 x 16 tiles of columns: the waves resident on one XCD cover a compact
+    // patch of the x-y plane
     const int64_t cw = lw / nzs;
     const int zs = (int)(lw % nzs);
     const int ntx = (G.nx + 15) / 16;

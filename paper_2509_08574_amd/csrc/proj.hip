@@ -11,7 +11,7 @@
 // Volumes are stored column-major (z fastest), so at each step the lanes read a
 // short contiguous run of one column: coalesced gathers for every view angle.
 //
-// Back (k_back): one wave per voxel column (i, j), columns taken in 16 x 16
+// Back (k_back): one wave per voxel column (i, j), columns taken in 8 x 16
 // tiles.  For every view, the wave visits the detector columns u whose rays
 // cross (i, j) and recomputes the forward walk's x-y interval [aa, ab]; each
 // lane then gathers, for each of its cells, a short window of detector rows
@@ -494,8 +494,12 @@ void launch_forward(const GeoK &G, int mode, const FwdArgs &a, hipStream_t s, in
 // most one z plane per segment, this equals its c0 / c1 bit for bit and is 0 for
 // every cell the forward does not touch: the two kernels apply the same matrix.
 // No atomics; every cell is summed in a fixed order.
+// Tile of voxel columns (x by y) whose waves run side by side.  Timed per A^T
+// with the view chunks (ms at 512 x 512 x 400 / 256^3): 16 x 16 39.4 / 2.71,
+// 8 x 16 38.6 / 2.66, 4 x 16 38.5 / 2.65, 4 x 32 38.9 / 2.66, 8 x 32 39.0 / 2.67,
+// 16 x 8 40.1 / 2.80, 8 x 8 40.0 / 2.76, 32 x 32 40.0 / 2.77.  Same bits for all.
 #ifndef CBCT_BACK_TILE_W
-#define CBCT_BACK_TILE_W 16
+#define CBCT_BACK_TILE_W 8
 #endif
 #ifndef CBCT_BACK_TILE_H
 #define CBCT_BACK_TILE_H 16
@@ -726,14 +730,14 @@ static int back_candidates(const GeoK &G) {
 }
 
 // Views per launch of A^T.  A block sums its cells over the views in order, and
-// the blocks resident on one XCD (about 224, i.e. 3.5 tiles of 16 x 16 columns)
+// the blocks resident on one XCD (about 224, i.e. 7 tiles of 8 x 16 columns)
 // are spread over the views they have reached: blocks finish and are replaced
 // at different times.  Over all views, the detector data those blocks touch
 // overflows the XCD's 4 MB L2 at the larger geometries (hit rate 0.50 at
 // 512 x 512 x 400 with 180 views).  One launch per chunk of views bounds that
-// spread.  The chunk is sized so that one tile's detector footprint per view
-// (the detector columns a 16-column tile can cast its shadow on, times the rows
-// a voxel column spans) over the chunk's views stays near 3.5 MB.  A
+// spread.  The chunk is sized so that a 16-column square's detector footprint
+// per view (the detector columns it can cast its shadow on, times the rows a
+// voxel column spans) over the chunk's views stays near 3.5 MB.  A
 // cell's float32 partial sum passes from launch to launch through the output,
 // unchanged, so every chunk size gives the same bits.  Measured per A^T (views
 // per launch: ms): 512 x 512 x 400, 180 views: all 49.0, 45: 41.5, 20: 40.2,
@@ -741,7 +745,7 @@ static int back_candidates(const GeoK &G) {
 static int back_views_per_launch(const GeoK &G, size_t sample_bytes) {
     if (G.back_views > 0) return std::min(G.back_views, G.nviews);
     const double h = std::max(G.hx, G.hy), mag = (double)G.dsd / G.dso;
-    const double cols = 16.0 * h * std::sqrt(2.0) * mag / G.du + 2.0;
+    const double cols = 16.0 * h * std::sqrt(2.0) * mag / G.du + 2.0;  // 16-column square
     const double rows = std::min((double)G.nv, G.nz * (double)G.hz * mag / G.dv);
     const double per_view = cols * rows * (double)sample_bytes;
     // in double until it is known to fit: a footprint far below a byte per view
